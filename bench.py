@@ -1,0 +1,238 @@
+"""Benchmark of the fused linear-LB step on one MI355X.
+
+Workload (default): the 4096 x 4096 two-layer medium with 20 seeded +-10 %
+anomalies, 64-node sponge, Ricker source at >= 20 nodes per wavelength and
+256 surface receivers; D2Q5, BGK tau = 1/2, FP32 populations.  One "step" is
+one time step of the whole grid (pull-stream, moments, per-node weights,
+linear equilibrium, collision, source, sponge, receiver sampling: one fused
+kernel launch).  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line: MLUPS (value), roofline of the step kernel (44
+algorithmic bytes per lattice update against the 8 TB/s HBM peak), a
+measured device-copy bandwidth, comparison variants (MRT, D2Q9, FP64,
+refinement) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D2Q5 FP32 MLUPS & % HBM roofline; served shots/s with p50/p99 latency"
+
+
+def bytes_per_lup(q, precision):
+    s = {"f32": 4, "f64": 8, "f16s": 2}[precision]
+    c = 8 if precision == "f64" else 4
+    return 2 * q * s + c
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_layered(lbwave, wl, q, collision, precision, cap):
+    g = lbwave.Grid(wl["nx"], wl["ny"], lattice=q, collision=collision, precision=precision,
+                    tau=0.5, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q],
+                    sponge_width=wl["sponge_width"], sponge_sigma_max=wl["sponge_sigma_max"],
+                    trace_capacity=cap, max_receivers=len(wl["receivers"]))
+    g.set_medium(wl["c2"])
+    g.set_source(wl["source"][0], wl["source"][1], wl["wavelet"])
+    g.record(wl["receivers"], fields=("p",))
+    return g
+
+
+def time_steps(torch, grid, steps, warmup):
+    """Warm up, then time exactly `steps` steps with events on the grid's
+    stream; returns seconds."""
+    if warmup:
+        grid.step(warmup)
+    grid.sync()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(grid.stream)
+    grid.step(steps)
+    end.record(grid.stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3
+
+
+def copy_bandwidth(torch, lbwave, nbytes=1 << 30, reps=20):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    lbwave.device_copy(b, a, nbytes)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        lbwave.device_copy(b, a, nbytes)
+    e.record()
+    e.synchronize()
+    t = s.elapsed_time(e) / 1e3 / reps
+    del a, b
+    return 2.0 * nbytes / t / 1e9
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or None when
+    the kernel source changed after the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_step_d2q5_bgk_f32_layered4096_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_1704_03172_amd", "csrc", "lb_kernels.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and l[:1].isalpha())
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(wl, target_s=10.0):
+    """The FP64 oracle (as it stands) on the same 4096^2 layered workload:
+    whole-grid steps until about target_s seconds have elapsed."""
+    from oracle import lb_oracle
+    g = lb_oracle.OracleGrid(wl["nx"], wl["ny"], q=5, collision="bgk", tau=0.5,
+                             sponge_width=wl["sponge_width"], sponge_sigma_max=wl["sponge_sigma_max"],
+                             source=wl["source"], wavelet=wl["wavelet"])
+    g.set_medium(wl["c2"])
+    g.set_state(np.zeros((wl["ny"], wl["nx"])))
+    g.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < target_s:
+        g.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    nodes = wl["nx"] * wl["ny"]
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": lb_oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d whole-grid steps of the 4096x4096 layered D2Q5 BGK workload "
+                      "(FP64, C loops, OpenMP over rows), %.1f s" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method's per-GPU share is the single-GPU kernel); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1704_03172_amd import inputs, lbwave
+    torch.cuda.set_device(0)
+    lbwave.lib()
+
+    steps, warmup = args.steps, args.warmup
+    log("building layered workload %d^2" % args.n)
+    wl = inputs.layered_workload(n=args.n, nsteps=steps + warmup + 1)
+    N = wl["nx"] * wl["ny"]
+    cap = steps + warmup + 1
+
+    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap)
+    log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
+    t = time_steps(torch, grid, steps, warmup)
+    mlups = N * steps / t / 1e6
+    kern_s = t / steps
+    bpl = bytes_per_lup(5, "f32")
+    achieved = bpl * N / kern_s / 1e9
+    tr = grid.traces[0].cpu().numpy()
+    finite = bool(np.isfinite(tr).all())
+    grid.close()
+    del grid
+    torch.cuda.empty_cache()
+
+    copy_gbs = copy_bandwidth(torch, lbwave)
+    log("copy kernel %.0f GB/s" % copy_gbs)
+
+    variants = {}
+    if not args.no_variants:
+        vsteps = 1000
+        for q, coll, prec in ((5, "mrt", "f32"), (9, "bgk", "f32"), (9, "mrt", "f32"),
+                              (5, "bgk", "f64"), (5, "bgk", "f16s")):
+            g = make_layered(lbwave, wl, q, coll, prec, vsteps + 11)
+            tv = time_steps(torch, g, vsteps, 10)
+            b = bytes_per_lup(q, prec)
+            variants["D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())] = {
+                "MLUPS": round(N * vsteps / tv / 1e6, 1),
+                "GBs": round(b * N * vsteps / tv / 1e9, 1),
+                "frac_hbm": round(b * N * vsteps / tv / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_lup": b, "steps": vsteps}
+            log("variant %s %.0f MLUPS" % (list(variants)[-1], N * vsteps / tv / 1e6))
+            g.close()
+            del g
+            torch.cuda.empty_cache()
+        # refinement: 2048^2 coarse D2Q5 MRT with the 1024 x 512 fine patch
+        rw = inputs.refined_workload(n=2048, nsteps=400)
+        g = lbwave.Grid(2048, 2048, lattice=5, collision="mrt", precision="f32",
+                        s=[1, 1, 1, 2, 2], sponge_width=rw["sponge_width"],
+                        sponge_sigma_max=rw["sponge_sigma_max"], patch=rw["patch"],
+                        trace_capacity=402, max_receivers=len(rw["receivers"]))
+        g.set_medium(rw["c2"])
+        g.set_medium(rw["c2_fine"], fine=True)
+        g.set_source(rw["source"][0], rw["source"][1], rw["wavelet"])
+        g.record(rw["receivers"])
+        tv = time_steps(torch, g, 300, 10)
+        nf = g.fine_shape[0] * g.fine_shape[1]
+        lups = 2048 * 2048 * 300 + 2 * nf * 300
+        variants["refined_D2Q5_MRT_F32_2048"] = {
+            "MLUPS": round(lups / tv / 1e6, 1), "coarse_steps": 300,
+            "fine_nodes": nf, "ms_per_coarse_step": round(tv / 300 * 1e3, 4)}
+        log("refined %.0f MLUPS" % (lups / tv / 1e6))
+        g.close()
+        del g
+
+    traffic = measured_traffic() if args.n == 4096 else None
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle sample (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(t / steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "layered two-layer medium + 20 anomalies, 4096x4096 "
+                               "(lattice units), 64-node sponge, Ricker source, 256 receivers",
+                   "nx": wl["nx"], "ny": wl["ny"], "lattice": "D2Q5", "collision": "BGK tau=1/2",
+                   "steps_timed": steps, "receivers": int(len(wl["receivers"]))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
+                     "kernel": "k_step<float,5,BGK,pull>", "bytes_per_lup": bpl,
+                     "avg_kernel_us": round(kern_s * 1e6, 3)},
+        "copy_kernel_GBs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
+        "traces_finite": finite,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * lbwave.h -- C-ABI of the MI355X (gfx950) linear lattice Boltzmann library
+ * for linear acoustic waves.
+ *
+ * The method is the linear lattice Boltzmann scheme of Dhuri, Hanasoge,
+ * Perlekar and Robertsson, "Numerical analysis of the lattice Boltzmann
+ * method for simulation of linear acoustic waves" (arXiv:1704.03172):
+ * D2Q5 and D2Q9 lattices (Table I, Appendix A), BGK (eq. BGK-LB) and MRT
+ * (eq. MRT-LB, moments of eq. D2Q5/D2Q9 moments) collision around the
+ * linear equilibrium g_i^eq = (w_i / c^2)(p + c_i . J) (eq. linear eqm
+ * dist, p = c^2 rho by eq. state), per-node sound speed through the lattice
+ * weights (Sec. II C, eq. LB lattice moments, eq. 0th lattice weight), a
+ * point source w_i S(n) (eq. MRT-LB linear acoustic, eq. source), absorbing
+ * sponge layers and a coarse/fine grid-refinement interface (Sec. IV,
+ * eq. grid refinement eqm dist, eq. coarse-fine dist connect).
+ *
+ * Conventions shared by every call
+ *  - Lattice units: dx = dt = 1.  Fields are row-major [ny][nx] (x fastest);
+ *    y is depth, row 0 the top.  Populations are stored structure-of-arrays.
+ *  - Every call returns LB_OK (0) or a negative LB_E_* code.  Argument and
+ *    range checks happen before anything is enqueued; on error nothing is
+ *    enqueued and the handle is unchanged.  An error raised by the HIP
+ *    runtime while enqueuing is kept on the handle ("sticky") and returned by
+ *    the next call and by lb_sync().  Nothing throws across this interface.
+ *  - A handle is bound to one HIP stream (passed as void*, a hipStream_t)
+ *    and is not thread-safe; distinct handles are independent.
+ *  - Memory: the caller allocates one device workspace of
+ *    lb_workspace_bytes() bytes and keeps it alive until lb_destroy_grid();
+ *    the library never allocates device memory.  Host arrays passed in are
+ *    copied before the call returns.  Device pointers passed in must stay
+ *    valid until the stream has executed the work that uses them.
+ *  - Time: the state at integer time n is the pre-collision population set.
+ *    One step n -> n+1 collides at every node (adding w_i S(n) at the source
+ *    node and damping in the sponge) and streams with periodic wrap.  Records
+ *    (receiver traces, sum of rho) for time n are written into column n.
+ */
+#ifndef LBWAVE_H
+#define LBWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define LB_OK             0
+#define LB_E_INVALID     -1  /* NULL handle/pointer, malformed argument     */
+#define LB_E_RANGE       -2  /* value outside its allowed range             */
+#define LB_E_UNSUPPORTED -3  /* valid combination this library does not do  */
+#define LB_E_WORKSPACE   -4  /* workspace missing or too small              */
+#define LB_E_HIP         -5  /* HIP runtime error (sticky on the handle)    */
+#define LB_E_STATE       -6  /* call out of order (e.g. step before medium) */
+
+/* ---- enumerations ----------------------------------------------------- */
+#define LB_D2Q5 5
+#define LB_D2Q9 9
+#define LB_BGK  0
+#define LB_MRT  1
+
+typedef enum {
+    LB_F32 = 0,   /* populations and arithmetic in FP32                     */
+    LB_F64 = 1,   /* populations and arithmetic in FP64                     */
+    LB_F16S = 2   /* populations stored as FP16, arithmetic in FP32         */
+} lb_dtype;
+
+/* field masks for lb_record / lb_get_field */
+#define LB_FIELD_P   1u  /* pressure p = c^2 rho (eq. state)                */
+#define LB_FIELD_RHO 2u  /* rho = sum_i g_i (eq. macroscopic density)       */
+#define LB_FIELD_JX  4u  /* J_x = sum_i c_ix g_i (eq. macroscopic velocity) */
+#define LB_FIELD_JY  8u  /* J_y = sum_i c_iy g_i                            */
+
+typedef struct lb_grid lb_grid;
+
+/*
+ * Grid descriptor.  Fill with lb_default_desc() and override fields.
+ *   nx, ny         lattice nodes (both >= 1, ny <= 65535).
+ *   lattice        LB_D2Q5 or LB_D2Q9 (velocity order of Appendix A).
+ *   collision      LB_BGK (relaxation time tau, omega = 1/tau; tau = 1/2 is
+ *                  the non-dissipative choice of Sec. II C) or LB_MRT.
+ *   precision      an lb_dtype.
+ *   tau            BGK relaxation time, tau >= 1/2.
+ *   s[9]           MRT inverse relaxation times in moment order (D2Q5:
+ *                  s_rho, s_v, s_v, s_e, s_p; D2Q9: s_rho, s_v, s_v, s_e,
+ *                  s_p, s_eps, s_q, s_q, s_p).  Rates of the conserved
+ *                  moments are ignored (they multiply zero); the others must
+ *                  lie in (0, 2].
+ *   d2q9_ratio     D2Q9 weight family r = w5 / w1 >= 0:
+ *                  w1 = c^2 / (2 + 4r), w5 = r w1, w0 = 1 - 4 w1 - 4 w5
+ *                  (r = 1/4 gives the conventional 4/9, 1/9, 1/36 at
+ *                  c^2 = 1/3; r = 0 gives the D2Q5 weights).
+ *   sponge_width   L >= 0: width of the absorbing frame along all four edges.
+ *   sponge_sigma_max  in [0, 1]: after each collision a node at distance d
+ *                  < L from the nearest edge is multiplied by
+ *                  1 - sigma_max ((L - d)/L)^2 (Sec. IV sponge layers).
+ *   patch_*        optional factor-2 refinement patch (D2Q5 only, omega = 2:
+ *                  BGK tau = 1/2 or MRT s_e = s_p = 2).  The patch covers
+ *                  coarse x in [patch_x0, patch_x0 + patch_nx], y likewise;
+ *                  the fine grid extends patch_overlap_out coarse cells
+ *                  beyond it; the coarse ring patch_overlap_in cells inside
+ *                  the patch receives the fine solution.
+ *   trace_capacity number of time columns of the trace / sum-rho arrays.
+ *   max_receivers  receivers that lb_record may register.
+ *   nbatch         independent shots sharing the grid shape (must be 1).
+ */
+typedef struct {
+    int32_t nx, ny;
+    int32_t lattice;
+    int32_t collision;
+    int32_t precision;
+    int32_t nbatch;
+    double tau;
+    double s[9];
+    double d2q9_ratio;
+    int32_t sponge_width;
+    int32_t _pad0;
+    double sponge_sigma_max;
+    int32_t patch_enable;
+    int32_t patch_x0, patch_y0, patch_nx, patch_ny;
+    int32_t patch_refine;
+    int32_t patch_overlap_out, patch_overlap_in;
+    int64_t trace_capacity;
+    int32_t max_receivers;
+    int32_t _pad1;
+} lb_grid_desc;
+
+/* Fill *d with defaults: 64 x 64 D2Q5 BGK FP32, tau = 1/2, MRT rates
+ * (1, 1, 1, 2, 2, 2, 1, 1, 2), ratio 1/4, no sponge, no patch,
+ * trace_capacity 0, max_receivers 0, nbatch 1. */
+void lb_default_desc(lb_grid_desc *d);
+
+/* Check a descriptor without a GPU.  Returns LB_OK or the error code that
+ * lb_create_grid would return for it. */
+int lb_validate_desc(const lb_grid_desc *d);
+
+/* Device bytes the workspace of a grid with this descriptor needs
+ * (two population buffers, c^2, receiver tables, reduction partials and,
+ * with a patch, the fine grid and its ring buffers).  0 if the descriptor
+ * is invalid. */
+size_t lb_workspace_bytes(const lb_grid_desc *d);
+
+/* Create a handle over a caller-owned device workspace of ws_bytes bytes
+ * (at least lb_workspace_bytes(d), 256-byte aligned) bound to `stream`.
+ * The state starts at rest (all populations 0, zeroed by a fill kernel
+ * enqueued on the stream) at time 0; c^2 is unset. */
+int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes,
+                   void *stream, lb_grid **out);
+
+/* Release the handle (not the workspace).  NULL-safe; waits for the stream. */
+int lb_destroy_grid(lb_grid *h);
+
+/* Squared lattice sound speed per node, [ny][nx] of type t (LB_F32 or
+ * LB_F64), on the host (on_device = 0) or device (1).  Rejects values
+ * outside (0, c2_max] with LB_E_RANGE, where c2_max = 1/2 for D2Q5
+ * (w0 >= 0, Appendix D) and (1 + 2r)/(2 + 2r) for D2Q9.  Synchronises the
+ * stream (the range check reads the result back). */
+int lb_set_medium(lb_grid *h, const void *c2, lb_dtype t, int on_device);
+
+/* Same for the fine grid of a patch: [nyf][nxf] with nxf = 2 (patch_nx +
+ * 2 overlap_out) + 1 and nyf likewise, sampled at the fine node positions
+ * (coarse coordinate X0 + i/2, Y0 + j/2, X0 = patch_x0 - overlap_out). */
+int lb_set_medium_fine(lb_grid *h, const void *c2, lb_dtype t, int on_device);
+
+/* Initial state g = g^eq(rho, J) at every node at time 0 (Sec. IV first
+ * bullet: initialise to equilibrium).  rho [ny][nx] required; jx, jy may be
+ * NULL (zero).  Needs the medium.  Resets time to 0 and the step counter. */
+int lb_set_state(lb_grid *h, const void *rho, const void *jx, const void *jy,
+                 lb_dtype t, int on_device);
+int lb_set_state_fine(lb_grid *h, const void *rho, const void *jx,
+                      const void *jy, lb_dtype t, int on_device);
+
+/* Point source at node (x, y) with amplitude S(n) = wavelet[n] for
+ * 0 <= n < nt and 0 afterwards (host array, copied).  nt = 0 removes it.
+ * The amplitude S(n) enters the collision of time n.  With a patch the
+ * source must lie outside the fine grid (LB_E_UNSUPPORTED otherwise). */
+int lb_set_source(lb_grid *h, int32_t x, int32_t y, const double *wavelet,
+                  int64_t nt);
+
+/* Register receivers (host array rxy[nrec][2] of (x, y), copied) and a
+ * caller-owned device trace array d_traces of the arithmetic type (float for
+ * LB_F32/LB_F16S, double for LB_F64), laid out [nfields][nrec][trace_capacity]
+ * where the fields are the bits of `what` in the order P, RHO, JX, JY.
+ * Column n receives the value at time n; times >= trace_capacity are an
+ * error for lb_step_n.  With a patch, receivers inside the patch read the
+ * coincident fine node at coarse times.  nrec = 0 disarms recording. */
+int lb_record(lb_grid *h, const int32_t *rxy, int32_t nrec, void *d_traces,
+              uint32_t what);
+
+/* Record the sum of rho over the grid at every time into d_sum[trace_capacity]
+ * (FP64, fixed reduction order, so bitwise reproducible).  NULL disarms.
+ * Not available with a patch. */
+int lb_record_sum_rho(lb_grid *h, double *d_sum);
+
+/* Enqueue n time steps (coarse steps with a patch) on the bound stream and
+ * return.  The first call after lb_set_state also performs the collision of
+ * time 0.  Each step is one fused pull-stream + collide launch. */
+int lb_step_n(lb_grid *h, int64_t n);
+
+/* Current time n of the handle (pre-collision state at time n). */
+int lb_get_time(const lb_grid *h, int64_t *n);
+
+/* Write one field (a single LB_FIELD_* bit) of the state at the current time
+ * into the device array d_out [ny][nx] of the arithmetic type. */
+int lb_get_field(lb_grid *h, uint32_t what, void *d_out);
+int lb_get_field_fine(lb_grid *h, uint32_t what, void *d_out);
+
+/* Raw state for checkpoint/resume: lb_state_bytes() bytes of device memory
+ * holding both population buffers and the time.  lb_set_raw_state() restores
+ * it into a handle with an identical descriptor; continuing from it is
+ * bitwise identical to never having stopped. */
+size_t lb_state_bytes(const lb_grid *h);
+int lb_get_state(lb_grid *h, void *d_out);
+int lb_set_raw_state(lb_grid *h, const void *d_in);
+
+/* Wait for all work enqueued by the handle; returns the sticky error. */
+int lb_sync(lb_grid *h);
+
+/* Static description of a status code. */
+const char *lb_status_string(int code);
+
+/* Plain device copy of `bytes` bytes (16-byte nontemporal vector loads and
+ * stores) on a stream: the measured reference for attainable HBM bandwidth.
+ * Both pointers 16-byte aligned, bytes a multiple of 16. */
+int lb_device_copy(void *d_dst, const void *d_src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBWAVE_H */

@@ -235,6 +235,14 @@ class OracleGrid:
         return {"p": self.pressure, "rho": self.rho, "jx": self.jx,
                 "jy": self.jy}[what]()
 
+    def fields_at(self, xs, ys):
+        """p, rho, jx, jy at the nodes (xs[k], ys[k]) only."""
+        gsel = self.g[:, ys, xs]                       # (q, k)
+        rho = gsel.sum(axis=0)
+        jx = self.c[:, 0].astype(np.float64) @ gsel
+        jy = self.c[:, 1].astype(np.float64) @ gsel
+        return {"p": self.c2[ys, xs] * rho, "rho": rho, "jx": jx, "jy": jy}
+
     def collide_node(self, gi, c2, s_here=0.0, sigma=0.0):
         """Steps 1-6 of the update at one node (used by the refinement)."""
         gi = np.ascontiguousarray(gi, dtype=np.float64)
@@ -267,9 +275,9 @@ def run(grid, nsteps, receivers=None, fields=("p",), sum_rho=False,
 
     def record(k):
         if nrec:
+            vals = grid.fields_at(rec[:, 0], rec[:, 1])
             for f, name in enumerate(fields):
-                fld = grid.field(name)
-                traces[f, :, k] = fld[rec[:, 1], rec[:, 0]]
+                traces[f, :, k] = vals[name]
         if sum_rho:
             sums[k] = grid.rho().sum()
         if grid.n in snaps:

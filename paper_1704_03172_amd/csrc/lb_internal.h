@@ -1,0 +1,130 @@
+// lb_internal.h -- kernel parameter blocks and launchers shared by the
+// runtime (lb_runtime.cpp) and the kernels (lb_kernels.hip).  Not part of
+// the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lbw {
+
+// Storage formats of the population arrays.
+enum Storage : int { ST_F32 = 0, ST_F64 = 1, ST_F16 = 2 };
+
+// Receivers of one grid: a CSR table over rows.  Within row y the entries
+// row_ptr[y] .. row_ptr[y+1]-1 hold the receiver x positions in ascending
+// order (xs) and the output slot of each (slot).
+struct Receivers {
+    const int32_t *row_ptr = nullptr;  // [ny + 1]; nullptr: nothing recorded
+    const int32_t *xs = nullptr;
+    const int32_t *slot = nullptr;
+    void *traces = nullptr;            // [nfields][nslots][cap], compute type
+    int32_t nslots = 0;                // receivers registered on the handle
+    uint32_t what = 0;                 // LB_FIELD_* mask
+    int64_t cap = 0;                   // columns per trace
+    int64_t col = 0;                   // column written by this launch
+};
+
+// Relaxation constants.  For MRT only the non-conserved moments matter:
+// srate[k] is s_k / |M_k|^2 for moment k (zero for conserved ones).
+struct Collision {
+    int32_t kind = 0;                  // LB_BGK or LB_MRT
+    double omega = 2.0;                // BGK 1/tau
+    double srate[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double kax = 0.5, kdg = 0.0;       // w_i / c^2 for axis / diagonal movers
+    double ratio = 0.0;                // D2Q9 w5 / w1
+};
+
+// One launch of the fused step (or of the collide-only variant).
+struct StepParams {
+    const void *src = nullptr;         // populations read
+    void *dst = nullptr;               // populations written
+    const void *c2 = nullptr;          // c^2 per node, compute type
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;               // elements between populations
+    int32_t q = 5;
+    Collision coll;
+    int32_t sponge_width = 0;
+    double sponge_smax = 0.0;
+    int32_t src_x = -1, src_y = -1;    // source node
+    double s_n = 0.0;                  // source amplitude of this time
+    Receivers rec;
+    double *partial = nullptr;         // per-block sums of rho (nullptr: off)
+};
+
+// Interface geometry of a factor-2 refinement patch (coarse units).
+struct PatchGeom {
+    int32_t X0 = 0, Y0 = 0;            // fine node (0, 0) at coarse (X0, Y0)
+    int32_t W = 0, H = 0;              // fine grid spans W x H coarse cells
+    int32_t nxf = 0, nyf = 0;          // 2W + 1, 2H + 1
+    int32_t xa = 0, xb = 0, ya = 0, yb = 0;   // coarse inner ring rectangle
+    int32_t nring = 0;                 // fine outer ring nodes
+    int32_t ninner = 0;                // coarse inner ring nodes
+    int32_t nsnap = 0;                 // coarse ring-line snapshot nodes
+};
+
+// A grid as seen by the interface kernels.
+struct GridRef {
+    const void *pop = nullptr;         // populations to read
+    int32_t pre = 0;                   // 1: pop holds the pre-collision state
+    const void *c2 = nullptr;
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;
+};
+
+struct InterfaceParams {
+    PatchGeom g;
+    GridRef coarse;                    // coarse state read
+    GridRef fine;                      // fine state read (restriction)
+    void *snap = nullptr;              // [5][nsnap] ring-line snapshot
+    double a_snap = 0.0, a_now = 1.0;  // prolongation: a_snap*snap + a_now*coarse
+    void *dst = nullptr;               // populations written (fine or coarse)
+    const void *dst_c2 = nullptr;      // c^2 of the written grid
+    int32_t dst_nx = 0, dst_ny = 0;
+    int64_t dst_pstride = 0;
+    double f = 1.0;                    // non-equilibrium rescaling factor
+    Collision coll;                    // collision of the written grid
+    int32_t sponge_width = 0;          // sponge of the written grid
+    double sponge_smax = 0.0;
+    uint32_t field = 0;                // nonzero: write this LB_FIELD_* of the
+    void *field_out = nullptr;         // interface state instead of populations
+};
+
+// Field extraction: one field of the state at the current time.
+struct FieldParams {
+    const void *pop = nullptr;
+    int32_t pre = 0;                   // 1: direct read; 0: pull from post-collision
+    const void *c2 = nullptr;
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;
+    int32_t q = 5;
+    uint32_t what = 0;
+    void *out = nullptr;
+};
+
+// Launchers (lb_kernels.hip).  All return the launch status.
+hipError_t launch_step(int storage, const StepParams &p, bool pull,
+                       hipStream_t s);
+int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
+hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
+                               double *out, hipStream_t s);
+hipError_t launch_equilibrium(int storage, int32_t q, void *pop,
+                              int64_t pstride, const void *c2,
+                              const void *rho, const void *jx, const void *jy,
+                              int in_f64, int32_t nx, int32_t ny,
+                              const Collision &coll, hipStream_t s);
+hipError_t launch_convert_c2(int storage, const void *in, int in_f64,
+                             void *out, int64_t n, double c2max,
+                             int32_t *bad_count, hipStream_t s);
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
+hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s);
+hipError_t launch_snapshot(int storage, const InterfaceParams &p,
+                           hipStream_t s);
+hipError_t launch_prolong(int storage, const InterfaceParams &p,
+                          hipStream_t s);
+hipError_t launch_restrict(int storage, const InterfaceParams &p,
+                           hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes,
+                       hipStream_t s);
+
+}  // namespace lbw

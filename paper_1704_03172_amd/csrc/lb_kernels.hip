@@ -1,0 +1,678 @@
+// lb_kernels.hip -- gfx950 kernels of the linear lattice Boltzmann scheme
+// (arXiv:1704.03172).
+//
+// Storage: populations structure-of-arrays, pop[i][y][x], x fastest, with a
+// stride of pstride elements between populations.  The step kernel keeps the
+// post-collision state: launch n reads h(n-1) = post-collision populations of
+// time n-1, pulls g_i(x, n) = h_i(x - c_i, n-1) (streaming, eq. BGK-LB lhs,
+// periodic wrap), records time n, collides (eq. BGK-LB / eq. MRT-LB around
+// eq. linear eqm dist), adds w_i S(n) at the source node (eq. MRT-LB linear
+// acoustic), damps in the sponge (Sec. IV) and writes h(n) at the node it
+// owns.  Every element of every array is read once and written once per
+// step: the kernel is HBM-bound (no data reuse to stage in LDS), so it is
+// written as a pure streaming pass with 16-byte vector accesses.
+//
+// Each thread owns V consecutive x-nodes of one row (V * sizeof(storage) =
+// 16 bytes).  Pulls along x are offset by one element; gfx950 accepts
+// 4-byte-aligned dwordx4 loads, so the shifted pulls are single vector loads
+// except at the periodic seam, which takes an element-wise path.  Population
+// and c^2 traffic is single-use, so loads and stores carry the nontemporal
+// hint (measured on MI355X: +8-11 % HBM throughput over cached accesses for
+// this 11-stream pattern, and +7 % for a plain copy).
+#include "lb_internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace lbw {
+namespace {
+
+constexpr int kBlock = 256;       // set-up, field and interface kernels
+constexpr int kStepBlock = 128;   // fused step (best of a block-size sweep)
+
+// ---- lattice tables (velocity order of Appendix A) -----------------------
+template <int Q>
+__host__ __device__ constexpr int cxv(int i) {
+    return Q == 5 ? (i == 1 ? 1 : i == 3 ? -1 : 0)
+                  : (i == 1 || i == 5 || i == 8 ? 1 : i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+template <int Q>
+__host__ __device__ constexpr int cyv(int i) {
+    return Q == 5 ? (i == 2 ? 1 : i == 4 ? -1 : 0)
+                  : (i == 2 || i == 5 || i == 6 ? 1 : i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+
+// Rows of the moment matrix of Appendix A (non-conserved rows only are
+// used: D2Q5 k = 3 (e), 4 (pxx); D2Q9 k = 3 (e), 4 (pxx), 5 (eps),
+// 6 (qx), 7 (qy), 8 (pxy)).
+template <int Q>
+__host__ __device__ constexpr int mrow(int k, int i) {
+    if (Q == 5) {
+        if (k == 3) return i == 0 ? -4 : 1;
+        if (k == 4) return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
+        return 0;
+    }
+    switch (k) {
+    case 3: return i == 0 ? -4 : (i <= 4 ? -1 : 2);
+    case 4: return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
+    case 5: return i == 0 ? 4 : (i <= 4 ? -2 : 1);
+    case 6: return i == 1 ? -2 : i == 3 ? 2 : (i == 5 || i == 8 ? 1 : (i == 6 || i == 7 ? -1 : 0));
+    case 7: return i == 2 ? -2 : i == 4 ? 2 : (i == 5 || i == 6 ? 1 : (i == 7 || i == 8 ? -1 : 0));
+    case 8: return i == 5 || i == 7 ? 1 : (i == 6 || i == 8 ? -1 : 0);
+    default: return 0;
+    }
+}
+
+// ---- storage traits -------------------------------------------------------
+template <typename S> struct Tr;
+template <> struct Tr<float> {
+    using T = float;
+    static constexpr int V = 4;
+    typedef float vec __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <> struct Tr<double> {
+    using T = double;
+    static constexpr int V = 2;
+    typedef double vec __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <> struct Tr<_Float16> {
+    using T = float;
+    static constexpr int V = 8;
+    typedef _Float16 vec __attribute__((ext_vector_type(8), aligned(2)));
+};
+
+__device__ inline int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// V consecutive elements starting at x = xs of one row, periodic in x.
+template <typename S, int V>
+__device__ inline void load_x(const S *__restrict__ row, int xs, int nx, S (&v)[V]) {
+    if (V > 1 && xs >= 0 && xs + V <= nx) {
+        typedef typename Tr<S>::vec vt;
+        vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(row + xs));
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = t[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = row[wrapi(xs + j, nx)];
+    }
+}
+
+template <typename S, int V>
+__device__ inline void store_x(S *__restrict__ row, int x0, int nx, const S (&v)[V]) {
+    if (V > 1 && x0 + V <= nx) {
+        typedef typename Tr<S>::vec vt;
+        vt t;
+#pragma unroll
+        for (int j = 0; j < V; ++j) t[j] = v[j];
+        __builtin_nontemporal_store(t, reinterpret_cast<vt *>(row + x0));
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            if (x0 + j < nx) row[x0 + j] = v[j];
+    }
+}
+
+// ---- the per-node update ---------------------------------------------------
+// Lattice weights from c^2 (Sec. II C): D2Q5 w_i = c^2/2 for movers,
+// w0 = 1 - 2 c^2; D2Q9 w1 = c^2 kax, w5 = r w1, w0 = 1 - 4 w1 - 4 w5.
+template <typename T, int Q>
+__device__ inline void weights(T c2, const Collision &c, T (&w)[Q]) {
+    if (Q == 5) {
+        T w1 = T(0.5) * c2;
+        w[0] = T(1) - T(4) * w1;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) w[i] = w1;
+    } else {
+        T w1 = c2 * T(c.kax);
+        T w5 = w1 * T(c.ratio);
+        w[0] = T(1) - T(4) * w1 - T(4) * w5;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) w[i] = i <= 4 ? w1 : w5;
+    }
+}
+
+// Collision of one node: out = g - C (g - g^eq) with the linear equilibrium
+// g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I, MRT
+// C = M^-1 S M applied through the non-conserved moments only.
+template <typename T, int Q, int KIND>
+__device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&out)[Q], T (&w)[Q]) {
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += g[i];
+        if (cxv<Q>(i) > 0) jx += g[i];
+        if (cxv<Q>(i) < 0) jx -= g[i];
+        if (cyv<Q>(i) > 0) jy += g[i];
+        if (cyv<Q>(i) < 0) jy -= g[i];
+    }
+    weights<T, Q>(c2, c, w);
+    T d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
+        T cj = T(cxv<Q>(i)) * jx + T(cyv<Q>(i)) * jy;
+        T geq = w[i] * rho + (i == 0 ? T(0) : kj * cj);
+        d[i] = g[i] - geq;
+    }
+    if (KIND == 0) {
+        const T om = T(c.omega);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[i] = g[i] - om * d[i];
+    } else {
+        T r[9];
+#pragma unroll
+        for (int k = 3; k < Q; ++k) {
+            T m = T(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int a = mrow<Q>(k, i);
+                if (a != 0) m += T(a) * d[i];
+            }
+            r[k] = T(c.srate[k]) * m;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 3; k < Q; ++k) {
+                int a = mrow<Q>(k, i);
+                if (a != 0) acc += T(a) * r[k];
+            }
+            out[i] = g[i] - acc;
+        }
+    }
+}
+
+template <typename T>
+__device__ inline T sponge_factor(int x, int y, int nx, int ny, int L, double smax) {
+    if (L <= 0) return T(1);
+    int d = min(min(x, y), min(nx - 1 - x, ny - 1 - y));
+    if (d >= L) return T(1);
+    T f = T(L - d) / T(L);
+    return T(1) - T(smax) * f * f;
+}
+
+template <typename T>
+__device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, T jy, T c2) {
+    T *tr = reinterpret_cast<T *>(rc.traces);
+    int f = 0;
+    const int64_t plane = (int64_t)rc.nslots * rc.cap;
+    const int64_t base = (int64_t)slot * rc.cap + rc.col;
+    if (rc.what & 1u) { tr[f * plane + base] = c2 * rho; ++f; }
+    if (rc.what & 2u) { tr[f * plane + base] = rho; ++f; }
+    if (rc.what & 4u) { tr[f * plane + base] = jx; ++f; }
+    if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
+}
+
+// ---- fused step -------------------------------------------------------------
+template <typename S, int Q, int KIND, bool PULL>
+__global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
+    using T = typename Tr<S>::T;
+    constexpr int V = PULL ? Tr<S>::V : 1;
+    const int y = blockIdx.y;
+    const int x0 = (blockIdx.x * kStepBlock + threadIdx.x) * V;
+    const int nx = p.nx, ny = p.ny;
+    const bool active = x0 < nx;
+    double local = 0.0;
+
+    if (active) {
+        const S *src = reinterpret_cast<const S *>(p.src);
+        T g[Q][V];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ys = PULL ? wrapi(y - cyv<Q>(i), ny) : y;
+            const S *row = src + i * p.pstride + (int64_t)ys * nx;
+            S t[V];
+            load_x<S, V>(row, PULL ? x0 - cxv<Q>(i) : x0, nx, t);
+#pragma unroll
+            for (int j = 0; j < V; ++j) g[i][j] = T(t[j]);
+        }
+        T c2v[V];
+        {
+            const T *c2row = reinterpret_cast<const T *>(p.c2) + (int64_t)y * nx;
+            if (V > 1 && x0 + V <= nx) {
+                typedef T ct __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+                ct t = __builtin_nontemporal_load(reinterpret_cast<const ct *>(c2row + x0));
+#pragma unroll
+                for (int j = 0; j < V; ++j) c2v[j] = t[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) c2v[j] = c2row[min(x0 + j, nx - 1)];
+            }
+        }
+
+        // receivers of this row (CSR lookup; rows without receivers cost one
+        // uniform pair of loads)
+        int rb = 0, re = 0;
+        if (p.rec.row_ptr) {
+            rb = p.rec.row_ptr[y];
+            re = p.rec.row_ptr[y + 1];
+        }
+
+        S outv[Q][V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            T gj[Q], gs[Q], w[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+            const int x = x0 + j;
+            if (rb < re && x < nx) {
+                T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    rho += gj[i];
+                    jx += T(cxv<Q>(i)) * gj[i];
+                    jy += T(cyv<Q>(i)) * gj[i];
+                }
+                int lo = rb, hi = re;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
+                }
+                for (; lo < re && p.rec.xs[lo] == x; ++lo)
+                    write_fields<T>(p.rec, p.rec.slot[lo], rho, jx, jy, c2v[j]);
+            }
+            if (p.partial && x < nx) {
+                T rho = T(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) rho += gj[i];
+                local += double(rho);
+            }
+            collide<T, Q, KIND>(gj, c2v[j], p.coll, gs, w);
+            if (y == p.src_y && x == p.src_x) {
+                const T sn = T(p.s_n);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+            }
+            const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) outv[i][j] = S(gs[i] * sf);
+        }
+        S *dst = reinterpret_cast<S *>(p.dst);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            store_x<S, V>(dst + i * p.pstride + (int64_t)y * nx, x0, nx, outv[i]);
+    }
+
+    if (p.partial) {   // uniform branch: per-block sum of rho in FP64
+        for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
+        __shared__ double sh[kStepBlock / 64];
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = local;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kStepBlock / 64; ++k) s += sh[k];
+            p.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_finalize(const double *partial, int64_t n, double *out) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += partial[i];
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---- set-up kernels --------------------------------------------------------
+template <typename S, int Q>
+__global__ __launch_bounds__(kBlock) void k_equilibrium(S *pop, int64_t pstride, const void *c2v,
+                                                        const void *rho, const void *jx, const void *jy,
+                                                        int in_f64, int64_t n, Collision c) {
+    using T = typename Tr<S>::T;
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    auto rd = [&](const void *a) -> double {
+        if (!a) return 0.0;
+        return in_f64 ? reinterpret_cast<const double *>(a)[k] : double(reinterpret_cast<const float *>(a)[k]);
+    };
+    T r = T(rd(rho)), x = T(rd(jx)), y = T(rd(jy));
+    T c2 = reinterpret_cast<const T *>(c2v)[k];
+    T w[Q];
+    weights<T, Q>(c2, c, w);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
+        T cj = T(cxv<Q>(i)) * x + T(cyv<Q>(i)) * y;
+        pop[i * pstride + k] = S(w[i] * r + (i == 0 ? T(0) : kj * cj));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_convert_c2(const void *in, int in_f64, T *out, int64_t n,
+                                                       double c2max, int32_t *bad) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    double v = in_f64 ? reinterpret_cast<const double *>(in)[k] : double(reinterpret_cast<const float *>(in)[k]);
+    if (!(v > 0.0 && v <= c2max)) atomicAdd(bad, 1);
+    out[k] = T(v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(uint32_t *p, int64_t nwords) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nwords; k += (int64_t)gridDim.x * kBlock)
+        p[k] = 0u;
+}
+
+typedef float f4a __attribute__((ext_vector_type(4)));
+// Reference copy: 16-byte nontemporal loads and stores, the access pattern of
+// the fused step reduced to one read and one write stream.
+__global__ __launch_bounds__(kBlock) void k_copy(f4a *__restrict__ dst, const f4a *__restrict__ src, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
+}
+
+// ---- fields of the current state ----------------------------------------------
+template <typename S, int Q>
+__global__ __launch_bounds__(kBlock) void k_field(FieldParams p) {
+    using T = typename Tr<S>::T;
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= (int64_t)p.nx * p.ny) return;
+    const int x = int(k % p.nx), y = int(k / p.nx);
+    const S *pop = reinterpret_cast<const S *>(p.pop);
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int xs = p.pre ? x : wrapi(x - cxv<Q>(i), p.nx);
+        int ys = p.pre ? y : wrapi(y - cyv<Q>(i), p.ny);
+        T gi = T(pop[i * p.pstride + (int64_t)ys * p.nx + xs]);
+        rho += gi;
+        jx += T(cxv<Q>(i)) * gi;
+        jy += T(cyv<Q>(i)) * gi;
+    }
+    T v = rho;
+    if (p.what == 1u) v = reinterpret_cast<const T *>(p.c2)[k] * rho;
+    else if (p.what == 4u) v = jx;
+    else if (p.what == 8u) v = jy;
+    reinterpret_cast<T *>(p.out)[k] = v;
+}
+
+// ---- refinement interface (D2Q5, factor 2) -------------------------------------
+template <typename S, typename T>
+__device__ inline void pre_at(const GridRef &r, int x, int y, T (&g)[5]) {
+    const S *pop = reinterpret_cast<const S *>(r.pop);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        int xs = r.pre ? x : wrapi(x - cxv<5>(i), r.nx);
+        int ys = r.pre ? y : wrapi(y - cyv<5>(i), r.ny);
+        g[i] = T(pop[i * r.pstride + (int64_t)ys * r.nx + xs]);
+    }
+}
+
+// Snapshot layout: top row (y = Y0, x = X0-1 .. X0+W+1), bottom row
+// (y = Y0+H), left column (x = X0, y = Y0-1 .. Y0+H+1), right column (x = X0+W).
+__device__ inline void snap_node(const PatchGeom &g, int t, int &x, int &y) {
+    const int nh = g.W + 3, nv = g.H + 3;
+    if (t < nh) { x = g.X0 - 1 + t; y = g.Y0; }
+    else if (t < 2 * nh) { x = g.X0 - 1 + (t - nh); y = g.Y0 + g.H; }
+    else if (t < 2 * nh + nv) { x = g.X0; y = g.Y0 - 1 + (t - 2 * nh); }
+    else { x = g.X0 + g.W; y = g.Y0 - 1 + (t - 2 * nh - nv); }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_snapshot(InterfaceParams p) {
+    using T = typename Tr<S>::T;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= p.g.nsnap) return;
+    int x, y;
+    snap_node(p.g, t, x, y);
+    T g[5];
+    pre_at<S, T>(p.coarse, x, y, g);
+    T *snap = reinterpret_cast<T *>(p.snap);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) snap[i * p.g.nsnap + t] = g[i];
+}
+
+// R_f(g) = g^eq(rho(g), J(g)) + f (g - g^eq) with the weights of the
+// receiving node's c^2 (eq. coarse-fine dist connect), then the collision
+// (and sponge) of the receiving grid; written as the post-collision state at
+// node (x, y) of dst.
+template <typename S, int KIND>
+__device__ inline void rescale_collide_store_impl(const InterfaceParams &p, typename Tr<S>::T (&gh)[5], int x, int y) {
+    using T = typename Tr<S>::T;
+    const int64_t k = (int64_t)y * p.dst_nx + x;
+    const T c2 = reinterpret_cast<const T *>(p.dst_c2)[k];
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        rho += gh[i];
+        jx += T(cxv<5>(i)) * gh[i];
+        jy += T(cyv<5>(i)) * gh[i];
+    }
+    if (p.field) {   // R_f keeps rho and J: the node's fields are those of gh
+        T v = p.field == 1u ? c2 * rho : p.field == 2u ? rho : p.field == 4u ? jx : jy;
+        reinterpret_cast<T *>(p.field_out)[k] = v;
+        return;
+    }
+    T w[5];
+    weights<T, 5>(c2, p.coll, w);
+    T gr[5], gs[5];
+    const T f = T(p.f);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        T geq = w[i] * rho + (i == 0 ? T(0) : T(0.5) * (T(cxv<5>(i)) * jx + T(cyv<5>(i)) * jy));
+        gr[i] = geq + f * (gh[i] - geq);
+    }
+    collide<T, 5, KIND>(gr, c2, p.coll, gs, w);
+    const T sf = sponge_factor<T>(x, y, p.dst_nx, p.dst_ny, p.sponge_width, p.sponge_smax);
+    S *dst = reinterpret_cast<S *>(p.dst);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dst[i * p.dst_pstride + k] = S(gs[i] * sf);
+}
+
+// Fine outer ring layout: top row (j = 0), bottom row (j = nyf-1), left
+// column (i = 0, j = 1 .. nyf-2), right column (i = nxf-1).
+template <typename S, int KIND>
+__global__ __launch_bounds__(kBlock) void k_prolong(InterfaceParams p) {
+    using T = typename Tr<S>::T;
+    int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= p.g.nring) return;
+    const PatchGeom &g = p.g;
+    int i, j;
+    if (r < g.nxf) { i = r; j = 0; }
+    else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
+    else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
+    else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
+
+    // stencil: coarse nodes (cx_s, cy_s), snapshot indices, weights
+    int nodes_x[4], nodes_y[4], sidx[4];
+    T wt[4];
+    const int nh = g.W + 3, nv = g.H + 3;
+    const bool horiz = (j == 0 || j == g.nyf - 1);
+    const int hbase = (j == 0) ? 0 : nh;                 // top / bottom arrays
+    const int vbase = 2 * nh + ((i == 0) ? 0 : nv);      // left / right arrays
+    if ((i & 1) == 0 && (j & 1) == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = g.X0 + i / 2;
+            nodes_y[s] = g.Y0 + j / 2;
+            wt[s] = s == 1 ? T(1) : T(0);
+            sidx[s] = horiz ? hbase + i / 2 + 1 : vbase + j / 2 + 1;
+        }
+    } else if (i & 1) {
+        const int a = g.X0 + (i - 1) / 2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = a - 1 + s;
+            nodes_y[s] = g.Y0 + j / 2;
+            sidx[s] = hbase + (i - 1) / 2 + s;
+        }
+        wt[0] = wt[3] = T(-1) / T(16);
+        wt[1] = wt[2] = T(9) / T(16);
+    } else {
+        const int b = g.Y0 + (j - 1) / 2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = g.X0 + i / 2;
+            nodes_y[s] = b - 1 + s;
+            sidx[s] = vbase + (j - 1) / 2 + s;
+        }
+        wt[0] = wt[3] = T(-1) / T(16);
+        wt[1] = wt[2] = T(9) / T(16);
+    }
+    T gh[5] = {T(0), T(0), T(0), T(0), T(0)};
+    const T *snap = reinterpret_cast<const T *>(p.snap);
+    const T an = T(p.a_now), as = T(p.a_snap);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (wt[s] == T(0)) continue;
+        T gn[5];
+        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            T v = an * gn[q];
+            if (p.a_snap != 0.0) v += as * snap[q * g.nsnap + sidx[s]];
+            gh[q] += wt[s] * v;
+        }
+    }
+    rescale_collide_store_impl<S, KIND>(p, gh, i, j);
+}
+
+template <typename S, int KIND>
+__global__ __launch_bounds__(kBlock) void k_restrict(InterfaceParams p) {
+    using T = typename Tr<S>::T;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= p.g.ninner) return;
+    const PatchGeom &g = p.g;
+    const int nxr = g.xb - g.xa + 1;
+    const int nyr = g.yb - g.ya - 1;
+    int x, y;
+    if (t < nxr) { x = g.xa + t; y = g.ya; }
+    else if (t < 2 * nxr) { x = g.xa + t - nxr; y = g.yb; }
+    else if (t < 2 * nxr + nyr) { x = g.xa; y = g.ya + 1 + t - 2 * nxr; }
+    else { x = g.xb; y = g.ya + 1 + t - 2 * nxr - nyr; }
+    T gf[5];
+    pre_at<S, T>(p.fine, 2 * (x - g.X0), 2 * (y - g.Y0), gf);
+    rescale_collide_store_impl<S, KIND>(p, gf, x, y);
+}
+
+// ---- dispatch helpers ----------------------------------------------------------
+inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+template <typename S>
+int vwidth(bool pull) { return pull ? Tr<S>::V : 1; }
+
+template <typename S>
+hipError_t step_dispatch(const StepParams &p, bool pull, hipStream_t s) {
+    const int V = vwidth<S>(pull);
+    dim3 grid((unsigned)(((int64_t)p.nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)), (unsigned)p.ny);
+    const int kind = p.coll.kind;
+#define LBW_LAUNCH(QQ, KK, PP) \
+    hipLaunchKernelGGL((k_step<S, QQ, KK, PP>), grid, dim3(kStepBlock), 0, s, p)
+    if (p.q == 5) {
+        if (kind == 0) { if (pull) LBW_LAUNCH(5, 0, true); else LBW_LAUNCH(5, 0, false); }
+        else { if (pull) LBW_LAUNCH(5, 1, true); else LBW_LAUNCH(5, 1, false); }
+    } else {
+        if (kind == 0) { if (pull) LBW_LAUNCH(9, 0, true); else LBW_LAUNCH(9, 0, false); }
+        else { if (pull) LBW_LAUNCH(9, 1, true); else LBW_LAUNCH(9, 1, false); }
+    }
+#undef LBW_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------------
+int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull) {
+    int V = storage == ST_F32 ? vwidth<float>(pull) : storage == ST_F64 ? vwidth<double>(pull) : vwidth<_Float16>(pull);
+    return (((int64_t)nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)) * ny;
+}
+
+hipError_t launch_step(int storage, const StepParams &p, bool pull, hipStream_t s) {
+    switch (storage) {
+    case ST_F32: return step_dispatch<float>(p, pull, s);
+    case ST_F64: return step_dispatch<double>(p, pull, s);
+    case ST_F16: return step_dispatch<_Float16>(p, pull, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sum_finalize(const double *partial, int64_t nblocks, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_equilibrium(int storage, int32_t q, void *pop, int64_t pstride, const void *c2,
+                              const void *rho, const void *jx, const void *jy, int in_f64,
+                              int32_t nx, int32_t ny, const Collision &coll, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny;
+    dim3 grid(blocks_for(n));
+#define LBW_EQ(SS, QQ) hipLaunchKernelGGL((k_equilibrium<SS, QQ>), grid, dim3(kBlock), 0, s, \
+                                          reinterpret_cast<SS *>(pop), pstride, c2, rho, jx, jy, in_f64, n, coll)
+    if (storage == ST_F32) { if (q == 5) LBW_EQ(float, 5); else LBW_EQ(float, 9); }
+    else if (storage == ST_F64) { if (q == 5) LBW_EQ(double, 5); else LBW_EQ(double, 9); }
+    else { if (q == 5) LBW_EQ(_Float16, 5); else LBW_EQ(_Float16, 9); }
+#undef LBW_EQ
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_c2(int storage, const void *in, int in_f64, void *out, int64_t n, double c2max,
+                             int32_t *bad, hipStream_t s) {
+    dim3 grid(blocks_for(n));
+    if (storage == ST_F64)
+        hipLaunchKernelGGL(k_convert_c2<double>, grid, dim3(kBlock), 0, s, in, in_f64,
+                           reinterpret_cast<double *>(out), n, c2max, bad);
+    else
+        hipLaunchKernelGGL(k_convert_c2<float>, grid, dim3(kBlock), 0, s, in, in_f64,
+                           reinterpret_cast<float *>(out), n, c2max, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {
+    int64_t words = bytes / 4;
+    if (words <= 0) return hipSuccess;
+    unsigned nb = (unsigned)std::min<int64_t>((words + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(p), words);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    int64_t n = (int64_t)(bytes / 16);
+    unsigned nb = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1 << 20);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlock), 0, s, reinterpret_cast<f4a *>(dst),
+                       reinterpret_cast<const f4a *>(src), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s) {
+    dim3 grid(blocks_for((int64_t)p.nx * p.ny));
+#define LBW_F(SS, QQ) hipLaunchKernelGGL((k_field<SS, QQ>), grid, dim3(kBlock), 0, s, p)
+    if (storage == ST_F32) { if (p.q == 5) LBW_F(float, 5); else LBW_F(float, 9); }
+    else if (storage == ST_F64) { if (p.q == 5) LBW_F(double, 5); else LBW_F(double, 9); }
+    else { if (p.q == 5) LBW_F(_Float16, 5); else LBW_F(_Float16, 9); }
+#undef LBW_F
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(int storage, const InterfaceParams &p, hipStream_t s) {
+    dim3 grid(blocks_for(p.g.nsnap));
+    if (storage == ST_F32) hipLaunchKernelGGL(k_snapshot<float>, grid, dim3(kBlock), 0, s, p);
+    else if (storage == ST_F64) hipLaunchKernelGGL(k_snapshot<double>, grid, dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL(k_snapshot<_Float16>, grid, dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+#define LBW_IFACE(KERNEL, N)                                                                       \
+    dim3 grid(blocks_for(N));                                                                      \
+    const bool mrt = p.coll.kind == 1;                                                             \
+    if (storage == ST_F32) { if (mrt) hipLaunchKernelGGL((KERNEL<float, 1>), grid, dim3(kBlock), 0, s, p); \
+                             else hipLaunchKernelGGL((KERNEL<float, 0>), grid, dim3(kBlock), 0, s, p); }   \
+    else if (storage == ST_F64) { if (mrt) hipLaunchKernelGGL((KERNEL<double, 1>), grid, dim3(kBlock), 0, s, p); \
+                                  else hipLaunchKernelGGL((KERNEL<double, 0>), grid, dim3(kBlock), 0, s, p); } \
+    else { if (mrt) hipLaunchKernelGGL((KERNEL<_Float16, 1>), grid, dim3(kBlock), 0, s, p);         \
+           else hipLaunchKernelGGL((KERNEL<_Float16, 0>), grid, dim3(kBlock), 0, s, p); }           \
+    return hipGetLastError();
+
+hipError_t launch_prolong(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong, p.g.nring) }
+hipError_t launch_restrict(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_restrict, p.g.ninner) }
+
+}  // namespace lbw

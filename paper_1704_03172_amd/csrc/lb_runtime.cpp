@@ -1,0 +1,838 @@
+// lb_runtime.cpp -- host side of the C-ABI declared in include/lbwave.h:
+// descriptor validation, workspace carving, set-up uploads, receiver tables,
+// the A/B buffer rotation of the fused step and the coarse/fine refinement
+// schedule (arXiv:1704.03172, Sec. IV).  The library never allocates device
+// memory; everything lives in the caller's workspace.
+#include "lbwave.h"
+#include "lb_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace {
+
+using lbw::Collision;
+using lbw::FieldParams;
+using lbw::InterfaceParams;
+using lbw::PatchGeom;
+using lbw::StepParams;
+
+constexpr uint64_t kStateMagic = 0x4c42574156453031ull;  // "LBWAVE01"
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+size_t storage_bytes(int p) { return p == LB_F64 ? 8 : (p == LB_F16S ? 2 : 4); }
+size_t compute_bytes(int p) { return p == LB_F64 ? 8 : 4; }
+int storage_kind(int p) { return p == LB_F64 ? lbw::ST_F64 : (p == LB_F16S ? lbw::ST_F16 : lbw::ST_F32); }
+
+// Row norms |M_k|^2 of the moment matrices of Appendix A.
+const double kNormD2Q5[5] = {5, 2, 2, 20, 4};
+const double kNormD2Q9[9] = {9, 6, 6, 36, 4, 36, 12, 12, 4};
+
+double c2_max(const lb_grid_desc *d) {
+    if (d->lattice == LB_D2Q5) return 0.5;
+    const double r = d->d2q9_ratio;
+    return (1.0 + 2.0 * r) / (2.0 + 2.0 * r);
+}
+
+bool omega_is_two(const lb_grid_desc *d) {
+    if (d->collision == LB_BGK) return d->tau == 0.5;
+    return d->s[3] == 2.0 && d->s[4] == 2.0;
+}
+
+PatchGeom patch_geom(const lb_grid_desc *d) {
+    PatchGeom g;
+    const int oo = d->patch_overlap_out, oi = d->patch_overlap_in;
+    g.X0 = d->patch_x0 - oo;
+    g.Y0 = d->patch_y0 - oo;
+    g.W = d->patch_nx + 2 * oo;
+    g.H = d->patch_ny + 2 * oo;
+    g.nxf = 2 * g.W + 1;
+    g.nyf = 2 * g.H + 1;
+    g.xa = d->patch_x0 + oi;
+    g.xb = d->patch_x0 + d->patch_nx - oi;
+    g.ya = d->patch_y0 + oi;
+    g.yb = d->patch_y0 + d->patch_ny - oi;
+    g.nring = 2 * g.nxf + 2 * (g.nyf - 2);
+    g.ninner = 2 * (g.xb - g.xa + 1) + 2 * (g.yb - g.ya - 1);
+    g.nsnap = 2 * (g.W + 3) + 2 * (g.H + 3);
+    return g;
+}
+
+int validate(const lb_grid_desc *d) {
+    if (!d) return LB_E_INVALID;
+    if (d->lattice != LB_D2Q5 && d->lattice != LB_D2Q9) return LB_E_INVALID;
+    if (d->collision != LB_BGK && d->collision != LB_MRT) return LB_E_INVALID;
+    if (d->precision != LB_F32 && d->precision != LB_F64 && d->precision != LB_F16S) return LB_E_INVALID;
+    if (d->nx < 1 || d->ny < 1 || d->ny > 65535 || d->nx > (1 << 24)) return LB_E_RANGE;
+    if (d->nbatch != 1) return LB_E_UNSUPPORTED;
+    if (d->collision == LB_BGK) {
+        if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return LB_E_RANGE;
+    } else {
+        for (int k = 3; k < d->lattice; ++k)
+            if (!(d->s[k] > 0.0 && d->s[k] <= 2.0)) return LB_E_RANGE;
+    }
+    if (d->lattice == LB_D2Q9 && !(d->d2q9_ratio >= 0.0 && std::isfinite(d->d2q9_ratio))) return LB_E_RANGE;
+    if (d->sponge_width < 0 || !(d->sponge_sigma_max >= 0.0 && d->sponge_sigma_max <= 1.0)) return LB_E_RANGE;
+    if (d->trace_capacity < 0 || d->max_receivers < 0) return LB_E_RANGE;
+    if (d->patch_enable) {
+        if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
+        if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
+        if (d->patch_overlap_out < 1 || d->patch_overlap_in < 1) return LB_E_RANGE;
+        if (d->patch_nx < 1 || d->patch_ny < 1) return LB_E_RANGE;
+        if (2 * d->patch_overlap_in >= std::min(d->patch_nx, d->patch_ny)) return LB_E_RANGE;
+        PatchGeom g = patch_geom(d);
+        const int L = d->sponge_width;
+        // the fine grid and the coarse ring-line stencil stay inside the
+        // grid and outside the sponge (the fine grid has no sponge)
+        if (g.X0 - 2 < L || g.Y0 - 2 < L) return LB_E_RANGE;
+        if (g.X0 + g.W + 2 > d->nx - 1 - L || g.Y0 + g.H + 2 > d->ny - 1 - L) return LB_E_RANGE;
+        if (g.nyf > 65535) return LB_E_RANGE;
+    }
+    return LB_OK;
+}
+
+struct Layout {
+    int64_t pstride = 0, fpstride = 0;
+    int64_t nblocks = 0;
+    size_t pop[2] = {0, 0}, c2 = 0, rrow = 0, rxs = 0, rslot = 0;
+    size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0;
+    size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, total = 0;
+};
+
+Layout make_layout(const lb_grid_desc *d) {
+    Layout L;
+    const size_t ss = storage_bytes(d->precision), ts = compute_bytes(d->precision);
+    const int64_t n = (int64_t)d->nx * d->ny;
+    // population stride: 256-element aligned, skewed by 1024 elements so
+    // that the population arrays of power-of-two grids do not alias in the
+    // low address bits
+    L.pstride = (int64_t)align_up((size_t)n + 1024, 256);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.pop[0] = take((size_t)d->lattice * L.pstride * ss);
+    L.pop[1] = take((size_t)d->lattice * L.pstride * ss);
+    L.c2 = take((size_t)n * ts);
+    L.rrow = take(((size_t)d->ny + 1) * 4);
+    L.rxs = take((size_t)std::max(d->max_receivers, 1) * 4);
+    L.rslot = take((size_t)std::max(d->max_receivers, 1) * 4);
+    // the collide-only launch (one node per thread) has the most blocks
+    L.nblocks = lbw::step_blocks(storage_kind(d->precision), d->nx, d->ny, false);
+    L.partial = take((size_t)L.nblocks * 8);
+    L.scratch = take(256);
+    if (d->patch_enable) {
+        PatchGeom g = patch_geom(d);
+        const int64_t nf = (int64_t)g.nxf * g.nyf;
+        L.fpstride = (int64_t)align_up((size_t)nf + 1024, 256);
+        L.fpop[0] = take(5 * (size_t)L.fpstride * ss);
+        L.fpop[1] = take(5 * (size_t)L.fpstride * ss);
+        L.fc2 = take((size_t)nf * ts);
+        L.frow = take(((size_t)g.nyf + 1) * 4);
+        L.fxs = take((size_t)std::max(d->max_receivers, 1) * 4);
+        L.fslot = take((size_t)std::max(d->max_receivers, 1) * 4);
+        L.snap = take(5 * (size_t)g.nsnap * ts);
+    }
+    L.total = off;
+    return L;
+}
+
+// One lattice (the main/coarse grid or the fine grid of a patch).
+struct Lattice {
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;
+    void *pop[2] = {nullptr, nullptr};
+    int cur = 0;           // buffer with the newest state
+    int prev_pre = 0;      // the other buffer holds a pre-collision state
+    void *c2 = nullptr;
+    bool medium = false;
+    int32_t *rrow = nullptr, *rxs = nullptr, *rslot = nullptr;
+    bool has_rec = false;
+    void *curp() const { return pop[cur]; }
+    void *prevp() const { return pop[1 - cur]; }
+};
+
+}  // namespace
+
+struct lb_grid {
+    lb_grid_desc d;
+    hipStream_t stream = nullptr;
+    int storage = 0;
+    size_t ssize = 4, tsize = 4;
+    int q = 5;
+    Collision coll;
+    Layout L;
+    char *ws = nullptr;
+    Lattice main, fine;
+    bool patch = false;
+    PatchGeom geom;
+    void *snap = nullptr;
+    double *partial = nullptr;
+    int32_t *scratch = nullptr;
+    int64_t t = 0;
+    bool collided = false;
+    int32_t sx = -1, sy = -1;
+    std::vector<double> wavelet;
+    int32_t nrec = 0;
+    void *traces = nullptr;
+    uint32_t what = 0;
+    double *sum_rho = nullptr;
+    int sticky = LB_OK;
+};
+
+namespace {
+
+int hip_fail(lb_grid *h, hipError_t e) {
+    if (e == hipSuccess) return LB_OK;
+    h->sticky = LB_E_HIP;
+    return LB_E_HIP;
+}
+
+#define LB_TRY(h, expr)                                   \
+    do {                                                  \
+        hipError_t e__ = (expr);                          \
+        if (e__ != hipSuccess) return hip_fail((h), e__); \
+    } while (0)
+
+double source_at(const lb_grid *h, int64_t n) {
+    if (h->sx < 0 || n < 0 || n >= (int64_t)h->wavelet.size()) return 0.0;
+    return h->wavelet[(size_t)n];
+}
+
+StepParams base_params(const lb_grid *h, const Lattice &g, bool is_main) {
+    StepParams p;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.pstride = g.pstride;
+    p.q = h->q;
+    p.coll = h->coll;
+    p.c2 = g.c2;
+    if (is_main) {
+        p.sponge_width = h->d.sponge_width;
+        p.sponge_smax = h->d.sponge_sigma_max;
+        p.src_x = h->sx;
+        p.src_y = h->sy;
+    }
+    return p;
+}
+
+void attach_receivers(const lb_grid *h, const Lattice &g, StepParams &p, int64_t col) {
+    if (!g.has_rec || h->nrec == 0) return;
+    p.rec.row_ptr = g.rrow;
+    p.rec.xs = g.rxs;
+    p.rec.slot = g.rslot;
+    p.rec.traces = h->traces;
+    p.rec.nslots = h->nrec;
+    p.rec.what = h->what;
+    p.rec.cap = h->d.trace_capacity;
+    p.rec.col = col;
+}
+
+// Launch one update of lattice g: pull-stream + collide (or collide only
+// when `pull` is false, for the state at time 0).  Records column `col`.
+int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, bool record, bool sum) {
+    StepParams p = base_params(h, g, is_main);
+    p.src = g.curp();
+    p.dst = g.prevp();
+    if (is_main) p.s_n = source_at(h, col);
+    if (record) attach_receivers(h, g, p, col);
+    if (sum) p.partial = h->partial;
+    LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
+    if (sum) {
+        const int64_t nb = lbw::step_blocks(h->storage, g.nx, g.ny, pull);
+        LB_TRY(h, lbw::launch_sum_finalize(h->partial, nb, h->sum_rho + col, h->stream));
+    }
+    g.cur = 1 - g.cur;
+    g.prev_pre = pull ? 0 : 1;
+    return LB_OK;
+}
+
+InterfaceParams iface_base(const lb_grid *h) {
+    InterfaceParams p;
+    p.g = h->geom;
+    p.coll = h->coll;
+    p.snap = h->snap;
+    return p;
+}
+
+lbw::GridRef ref_prev(const Lattice &g) {
+    lbw::GridRef r;
+    r.pop = g.prevp();
+    r.pre = g.prev_pre;
+    r.c2 = g.c2;
+    r.nx = g.nx;
+    r.ny = g.ny;
+    r.pstride = g.pstride;
+    return r;
+}
+
+// Overwrite the fine outer ring (post-collision buffer `cur`) from the coarse
+// state held in the coarse `prev` buffer: a_snap * snapshot + a_now * coarse.
+int prolong(lb_grid *h, double a_snap, double a_now) {
+    InterfaceParams p = iface_base(h);
+    p.coarse = ref_prev(h->main);
+    p.a_snap = a_snap;
+    p.a_now = a_now;
+    p.dst = h->fine.curp();
+    p.dst_c2 = h->fine.c2;
+    p.dst_nx = h->fine.nx;
+    p.dst_ny = h->fine.ny;
+    p.dst_pstride = h->fine.pstride;
+    p.f = 0.5;
+    LB_TRY(h, lbw::launch_prolong(h->storage, p, h->stream));
+    return LB_OK;
+}
+
+// Overwrite the coarse inner ring (post-collision buffer `cur`) from the
+// coincident fine nodes of the state held in the fine `prev` buffer.
+int restrict_ring(lb_grid *h) {
+    InterfaceParams p = iface_base(h);
+    p.fine = ref_prev(h->fine);
+    p.dst = h->main.curp();
+    p.dst_c2 = h->main.c2;
+    p.dst_nx = h->main.nx;
+    p.dst_ny = h->main.ny;
+    p.dst_pstride = h->main.pstride;
+    p.f = 2.0;
+    p.sponge_width = h->d.sponge_width;
+    p.sponge_smax = h->d.sponge_sigma_max;
+    LB_TRY(h, lbw::launch_restrict(h->storage, p, h->stream));
+    return LB_OK;
+}
+
+int snapshot(lb_grid *h) {
+    InterfaceParams p = iface_base(h);
+    p.coarse = ref_prev(h->main);
+    LB_TRY(h, lbw::launch_snapshot(h->storage, p, h->stream));
+    return LB_OK;
+}
+
+bool recording(const lb_grid *h) { return h->nrec > 0 && h->traces; }
+
+int initial_collision(lb_grid *h) {
+    int rc;
+    const bool rec = recording(h), sum = h->sum_rho != nullptr;
+    if ((rc = launch_update(h, h->main, true, false, h->t, rec, sum))) return rc;
+    if (h->patch) {
+        if ((rc = launch_update(h, h->fine, false, false, h->t, rec, false))) return rc;
+        if ((rc = prolong(h, 0.0, 1.0))) return rc;
+        if ((rc = restrict_ring(h))) return rc;
+    }
+    h->collided = true;
+    return LB_OK;
+}
+
+int one_step(lb_grid *h) {
+    int rc;
+    const bool rec = recording(h), sum = h->sum_rho != nullptr;
+    const int64_t col = h->t + 1;
+    if (!h->patch) {
+        if ((rc = launch_update(h, h->main, true, true, col, rec, sum))) return rc;
+        h->t = col;
+        return LB_OK;
+    }
+    // Coarse step T -> T+2 in fine time units (Sec. IV schedule).
+    if ((rc = snapshot(h))) return rc;                                  // coarse ring at T
+    if ((rc = launch_update(h, h->main, true, true, col, rec, false))) return rc;   // coarse to T+2
+    if ((rc = launch_update(h, h->fine, false, true, col, false, false))) return rc; // fine to T+1
+    if ((rc = prolong(h, 0.5, 0.5))) return rc;                         // ring at T+1
+    if ((rc = launch_update(h, h->fine, false, true, col, rec, false))) return rc;  // fine to T+2
+    if ((rc = prolong(h, 0.0, 1.0))) return rc;                         // ring at T+2
+    if ((rc = restrict_ring(h))) return rc;                             // coarse ring at T+2
+    h->t = col;
+    return LB_OK;
+}
+
+int upload_sync(lb_grid *h, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return LB_OK;
+    LB_TRY(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+    LB_TRY(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int set_medium_impl(lb_grid *h, Lattice &g, const void *c2, lb_dtype t, int on_device) {
+    if (!h || !c2) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (t != LB_F32 && t != LB_F64) return LB_E_INVALID;
+    const int64_t n = (int64_t)g.nx * g.ny;
+    const double cmax = c2_max(&h->d);
+    g.medium = false;
+    if (!on_device) {
+        const bool in64 = t == LB_F64;
+        if (h->tsize == 8) {
+            std::vector<double> v((size_t)n);
+            for (int64_t k = 0; k < n; ++k) {
+                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
+                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
+                v[(size_t)k] = x;
+            }
+            int rc = upload_sync(h, g.c2, v.data(), (size_t)n * 8);
+            if (rc) return rc;
+        } else {
+            std::vector<float> v((size_t)n);
+            for (int64_t k = 0; k < n; ++k) {
+                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
+                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
+                v[(size_t)k] = (float)x;
+            }
+            int rc = upload_sync(h, g.c2, v.data(), (size_t)n * 4);
+            if (rc) return rc;
+        }
+    } else {
+        LB_TRY(h, lbw::launch_fill_zero(h->scratch, 256, h->stream));
+        LB_TRY(h, lbw::launch_convert_c2(h->storage, c2, t == LB_F64, g.c2, n, cmax, h->scratch, h->stream));
+        int32_t bad = 0;
+        LB_TRY(h, hipMemcpyAsync(&bad, h->scratch, 4, hipMemcpyDeviceToHost, h->stream));
+        LB_TRY(h, hipStreamSynchronize(h->stream));
+        if (bad) return LB_E_RANGE;
+    }
+    g.medium = true;
+    return LB_OK;
+}
+
+int set_state_impl(lb_grid *h, Lattice &g, const void *rho, const void *jx, const void *jy, lb_dtype t,
+                   int on_device) {
+    if (!h || !rho) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (t != LB_F32 && t != LB_F64) return LB_E_INVALID;
+    if (!g.medium) return LB_E_STATE;
+    const int q = (&g == &h->fine) ? 5 : h->q;
+    const int64_t n = (int64_t)g.nx * g.ny;
+    g.cur = 0;
+    g.prev_pre = 0;
+    if (on_device) {
+        LB_TRY(h, lbw::launch_equilibrium(h->storage, q, g.pop[0], g.pstride, g.c2, rho, jx, jy, t == LB_F64,
+                                          g.nx, g.ny, h->coll, h->stream));
+    } else {
+        // stage the host fields in the other population buffer, in chunks of
+        // nodes that fit it (the equilibrium is node-local)
+        const size_t es = t == LB_F64 ? 8 : 4;
+        const size_t cap_bytes = (size_t)q * g.pstride * h->ssize;
+        const int64_t chunk = (int64_t)(cap_bytes / (3 * es)) / 64 * 64;
+        if (chunk < 64) return LB_E_WORKSPACE;
+        char *stage = (char *)g.pop[1];
+        for (int64_t off = 0; off < n; off += chunk) {
+            const int64_t cnt = std::min<int64_t>(chunk, n - off);
+            const size_t bytes = (size_t)cnt * es;
+            char *s_rho = stage, *s_jx = stage + bytes, *s_jy = stage + 2 * bytes;
+            LB_TRY(h, hipMemcpyAsync(s_rho, (const char *)rho + off * es, bytes, hipMemcpyHostToDevice, h->stream));
+            if (jx) LB_TRY(h, hipMemcpyAsync(s_jx, (const char *)jx + off * es, bytes, hipMemcpyHostToDevice, h->stream));
+            if (jy) LB_TRY(h, hipMemcpyAsync(s_jy, (const char *)jy + off * es, bytes, hipMemcpyHostToDevice, h->stream));
+            char *dst = (char *)g.pop[0] + (size_t)off * h->ssize;
+            const char *c2p = (const char *)g.c2 + (size_t)off * h->tsize;
+            LB_TRY(h, lbw::launch_equilibrium(h->storage, q, dst, g.pstride, c2p, s_rho, jx ? s_jx : nullptr,
+                                              jy ? s_jy : nullptr, t == LB_F64, (int32_t)cnt, 1, h->coll,
+                                              h->stream));
+            LB_TRY(h, hipStreamSynchronize(h->stream));
+        }
+    }
+    if (&g == &h->main) {
+        h->t = 0;
+        h->collided = false;
+        if (h->patch) {   // the fine grid restarts at rest (lb_set_state_fine may follow)
+            Lattice &f = h->fine;
+            f.cur = 0;
+            f.prev_pre = 0;
+            const size_t fb = (size_t)((char *)f.pop[1] - (char *)f.pop[0]) + 5 * (size_t)f.pstride * h->ssize;
+            LB_TRY(h, lbw::launch_fill_zero(f.pop[0], (int64_t)fb, h->stream));
+        }
+    }
+    return LB_OK;
+}
+
+int get_field_impl(lb_grid *h, Lattice &g, int q, uint32_t what, void *out) {
+    if (!h || !out) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (what != LB_FIELD_P && what != LB_FIELD_RHO && what != LB_FIELD_JX && what != LB_FIELD_JY)
+        return LB_E_INVALID;
+    if (!g.medium) return LB_E_STATE;
+    FieldParams p;
+    if (h->collided) {
+        p.pop = g.prevp();
+        p.pre = g.prev_pre;
+    } else {
+        p.pop = g.curp();
+        p.pre = 1;
+    }
+    p.c2 = g.c2;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.pstride = g.pstride;
+    p.q = q;
+    p.what = what;
+    p.out = out;
+    LB_TRY(h, lbw::launch_field(h->storage, p, h->stream));
+    if (h->patch && h->collided) {
+        // nodes overwritten by the interface hold R_f of the other grid's
+        // state; R_f keeps rho and J, so their fields come from that state
+        InterfaceParams ip = iface_base(h);
+        ip.field = what;
+        ip.field_out = out;
+        if (&g == &h->main) {
+            ip.fine = ref_prev(h->fine);
+            ip.dst_c2 = h->main.c2;
+            ip.dst_nx = h->main.nx;
+            ip.dst_ny = h->main.ny;
+            LB_TRY(h, lbw::launch_restrict(h->storage, ip, h->stream));
+        } else {
+            ip.coarse = ref_prev(h->main);
+            ip.a_snap = 0.0;
+            ip.a_now = 1.0;
+            ip.dst_c2 = h->fine.c2;
+            ip.dst_nx = h->fine.nx;
+            ip.dst_ny = h->fine.ny;
+            LB_TRY(h, lbw::launch_prolong(h->storage, ip, h->stream));
+        }
+    }
+    return LB_OK;
+}
+
+// Receiver tables: CSR over rows, x ascending within a row.
+struct Rec { int32_t x, y, slot; };
+
+int upload_receivers(lb_grid *h, Lattice &g, std::vector<Rec> &v) {
+    g.has_rec = !v.empty();
+    if (v.empty()) return LB_OK;
+    std::sort(v.begin(), v.end(), [](const Rec &a, const Rec &b) {
+        return a.y != b.y ? a.y < b.y : (a.x != b.x ? a.x < b.x : a.slot < b.slot);
+    });
+    std::vector<int32_t> row((size_t)g.ny + 1, 0), xs(v.size()), slot(v.size());
+    for (const Rec &r : v) row[(size_t)r.y + 1]++;
+    for (int y = 0; y < g.ny; ++y) row[(size_t)y + 1] += row[(size_t)y];
+    for (size_t k = 0; k < v.size(); ++k) {
+        xs[k] = v[k].x;
+        slot[k] = v[k].slot;
+    }
+    int rc;
+    if ((rc = upload_sync(h, g.rrow, row.data(), row.size() * 4))) return rc;
+    if ((rc = upload_sync(h, g.rxs, xs.data(), xs.size() * 4))) return rc;
+    if ((rc = upload_sync(h, g.rslot, slot.data(), slot.size() * 4))) return rc;
+    return LB_OK;
+}
+
+struct StateHeader {
+    uint64_t magic;
+    int64_t t;
+    int32_t collided, nx, ny, q, precision, patch;
+    int32_t main_prev_pre, fine_prev_pre;
+    uint64_t bytes;
+};
+
+}  // namespace
+
+extern "C" {
+
+void lb_default_desc(lb_grid_desc *d) {
+    if (!d) return;
+    std::memset(d, 0, sizeof(*d));
+    d->nx = 64;
+    d->ny = 64;
+    d->lattice = LB_D2Q5;
+    d->collision = LB_BGK;
+    d->precision = LB_F32;
+    d->nbatch = 1;
+    d->tau = 0.5;
+    const double s[9] = {1, 1, 1, 2, 2, 2, 1, 1, 2};
+    for (int k = 0; k < 9; ++k) d->s[k] = s[k];
+    d->d2q9_ratio = 0.25;
+    d->patch_refine = 2;
+    d->patch_overlap_out = 2;
+    d->patch_overlap_in = 2;
+}
+
+int lb_validate_desc(const lb_grid_desc *d) { return validate(d); }
+
+size_t lb_workspace_bytes(const lb_grid_desc *d) {
+    if (validate(d) != LB_OK) return 0;
+    return make_layout(d).total;
+}
+
+int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes, void *stream, lb_grid **out) {
+    if (!out) return LB_E_INVALID;
+    *out = nullptr;
+    int rc = validate(d);
+    if (rc) return rc;
+    Layout L = make_layout(d);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u)) return LB_E_WORKSPACE;
+    lb_grid *h = new (std::nothrow) lb_grid();
+    if (!h) return LB_E_INVALID;
+    h->d = *d;
+    h->stream = (hipStream_t)stream;
+    h->storage = storage_kind(d->precision);
+    h->ssize = storage_bytes(d->precision);
+    h->tsize = compute_bytes(d->precision);
+    h->q = d->lattice;
+    h->L = L;
+    h->ws = (char *)d_workspace;
+    Collision &c = h->coll;
+    c.kind = d->collision;
+    c.omega = 1.0 / d->tau;
+    const double *norm = d->lattice == LB_D2Q5 ? kNormD2Q5 : kNormD2Q9;
+    for (int k = 0; k < 9; ++k) c.srate[k] = (k >= 3 && k < d->lattice) ? d->s[k] / norm[k] : 0.0;
+    c.ratio = d->lattice == LB_D2Q9 ? d->d2q9_ratio : 0.0;
+    c.kax = d->lattice == LB_D2Q9 ? 1.0 / (2.0 + 4.0 * c.ratio) : 0.5;
+    c.kdg = d->lattice == LB_D2Q9 ? c.ratio / (2.0 + 4.0 * c.ratio) : 0.0;
+
+    Lattice &m = h->main;
+    m.nx = d->nx;
+    m.ny = d->ny;
+    m.pstride = L.pstride;
+    m.pop[0] = h->ws + L.pop[0];
+    m.pop[1] = h->ws + L.pop[1];
+    m.c2 = h->ws + L.c2;
+    m.rrow = (int32_t *)(h->ws + L.rrow);
+    m.rxs = (int32_t *)(h->ws + L.rxs);
+    m.rslot = (int32_t *)(h->ws + L.rslot);
+    h->partial = (double *)(h->ws + L.partial);
+    h->scratch = (int32_t *)(h->ws + L.scratch);
+    size_t zero_bytes = L.pop[1] + (size_t)h->q * L.pstride * h->ssize;   // both buffers
+    if (d->patch_enable) {
+        h->patch = true;
+        h->geom = patch_geom(d);
+        Lattice &f = h->fine;
+        f.nx = h->geom.nxf;
+        f.ny = h->geom.nyf;
+        f.pstride = L.fpstride;
+        f.pop[0] = h->ws + L.fpop[0];
+        f.pop[1] = h->ws + L.fpop[1];
+        f.c2 = h->ws + L.fc2;
+        f.rrow = (int32_t *)(h->ws + L.frow);
+        f.rxs = (int32_t *)(h->ws + L.fxs);
+        f.rslot = (int32_t *)(h->ws + L.fslot);
+        h->snap = h->ws + L.snap;
+    }
+    // the state starts at rest: zero both population buffers of each grid
+    hipError_t e = lbw::launch_fill_zero(m.pop[0], (int64_t)zero_bytes, h->stream);
+    if (e == hipSuccess && h->patch)
+        e = lbw::launch_fill_zero(h->fine.pop[0], (int64_t)(L.fpop[1] - L.fpop[0] + 5 * (size_t)L.fpstride * h->ssize),
+                                  h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return LB_E_HIP;
+    }
+    *out = h;
+    return LB_OK;
+}
+
+int lb_destroy_grid(lb_grid *h) {
+    if (!h) return LB_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    int rc = h->sticky ? h->sticky : (e == hipSuccess ? LB_OK : LB_E_HIP);
+    delete h;
+    return rc;
+}
+
+int lb_set_medium(lb_grid *h, const void *c2, lb_dtype t, int on_device) {
+    if (!h) return LB_E_INVALID;
+    return set_medium_impl(h, h->main, c2, t, on_device);
+}
+
+int lb_set_medium_fine(lb_grid *h, const void *c2, lb_dtype t, int on_device) {
+    if (!h) return LB_E_INVALID;
+    if (!h->patch) return LB_E_STATE;
+    return set_medium_impl(h, h->fine, c2, t, on_device);
+}
+
+int lb_set_state(lb_grid *h, const void *rho, const void *jx, const void *jy, lb_dtype t, int on_device) {
+    if (!h) return LB_E_INVALID;
+    return set_state_impl(h, h->main, rho, jx, jy, t, on_device);
+}
+
+int lb_set_state_fine(lb_grid *h, const void *rho, const void *jx, const void *jy, lb_dtype t, int on_device) {
+    if (!h) return LB_E_INVALID;
+    if (!h->patch) return LB_E_STATE;
+    if (h->collided) return LB_E_STATE;
+    return set_state_impl(h, h->fine, rho, jx, jy, t, on_device);
+}
+
+int lb_set_source(lb_grid *h, int32_t x, int32_t y, const double *wavelet, int64_t nt) {
+    if (!h) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (nt < 0 || (nt > 0 && !wavelet)) return LB_E_INVALID;
+    if (nt == 0) {
+        h->sx = h->sy = -1;
+        h->wavelet.clear();
+        return LB_OK;
+    }
+    if (x < 0 || y < 0 || x >= h->d.nx || y >= h->d.ny) return LB_E_RANGE;
+    if (h->patch) {
+        const PatchGeom &g = h->geom;
+        if (x >= g.X0 - 1 && x <= g.X0 + g.W + 1 && y >= g.Y0 - 1 && y <= g.Y0 + g.H + 1) return LB_E_UNSUPPORTED;
+    }
+    try {
+        h->wavelet.assign(wavelet, wavelet + nt);
+    } catch (...) {
+        return LB_E_INVALID;
+    }
+    h->sx = x;
+    h->sy = y;
+    return LB_OK;
+}
+
+int lb_record(lb_grid *h, const int32_t *rxy, int32_t nrec, void *d_traces, uint32_t what) {
+    if (!h) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (nrec == 0) {
+        h->nrec = 0;
+        h->traces = nullptr;
+        h->what = 0;
+        h->main.has_rec = h->fine.has_rec = false;
+        return LB_OK;
+    }
+    if (nrec < 0 || !rxy || !d_traces) return LB_E_INVALID;
+    if (what == 0 || (what & ~0xFu)) return LB_E_INVALID;
+    if (nrec > h->d.max_receivers) return LB_E_RANGE;
+    std::vector<Rec> vm, vf;
+    const PatchGeom &g = h->geom;
+    for (int32_t r = 0; r < nrec; ++r) {
+        int32_t x = rxy[2 * r], y = rxy[2 * r + 1];
+        if (x < 0 || y < 0 || x >= h->d.nx || y >= h->d.ny) return LB_E_RANGE;
+        const bool in_patch = h->patch && x >= h->d.patch_x0 && x < h->d.patch_x0 + h->d.patch_nx &&
+                              y >= h->d.patch_y0 && y < h->d.patch_y0 + h->d.patch_ny;
+        if (in_patch) vf.push_back({2 * (x - g.X0), 2 * (y - g.Y0), r});
+        else vm.push_back({x, y, r});
+    }
+    int rc;
+    if ((rc = upload_receivers(h, h->main, vm))) return rc;
+    if (h->patch && (rc = upload_receivers(h, h->fine, vf))) return rc;
+    h->nrec = nrec;
+    h->traces = d_traces;
+    h->what = what;
+    return LB_OK;
+}
+
+int lb_record_sum_rho(lb_grid *h, double *d_sum) {
+    if (!h) return LB_E_INVALID;
+    if (h->patch && d_sum) return LB_E_UNSUPPORTED;
+    h->sum_rho = d_sum;
+    return LB_OK;
+}
+
+int lb_step_n(lb_grid *h, int64_t n) {
+    if (!h) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (n < 0) return LB_E_RANGE;
+    if (!h->main.medium || (h->patch && !h->fine.medium)) return LB_E_STATE;
+    if ((recording(h) || h->sum_rho) && h->t + n >= h->d.trace_capacity) return LB_E_RANGE;
+    int rc;
+    if (!h->collided && (rc = initial_collision(h))) return rc;
+    for (int64_t k = 0; k < n; ++k)
+        if ((rc = one_step(h))) return rc;
+    return LB_OK;
+}
+
+int lb_get_time(const lb_grid *h, int64_t *n) {
+    if (!h || !n) return LB_E_INVALID;
+    *n = h->t;
+    return LB_OK;
+}
+
+int lb_get_field(lb_grid *h, uint32_t what, void *d_out) {
+    if (!h) return LB_E_INVALID;
+    return get_field_impl(h, h->main, h->q, what, d_out);
+}
+
+int lb_get_field_fine(lb_grid *h, uint32_t what, void *d_out) {
+    if (!h) return LB_E_INVALID;
+    if (!h->patch) return LB_E_STATE;
+    return get_field_impl(h, h->fine, 5, what, d_out);
+}
+
+size_t lb_state_bytes(const lb_grid *h) {
+    if (!h) return 0;
+    size_t b = 256 + 2 * (size_t)h->q * h->main.pstride * h->ssize;
+    if (h->patch) b += 2 * 5 * (size_t)h->fine.pstride * h->ssize;
+    return b;
+}
+
+int lb_get_state(lb_grid *h, void *d_out) {
+    if (!h || !d_out) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    StateHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    hd.magic = kStateMagic;
+    hd.t = h->t;
+    hd.collided = h->collided;
+    hd.nx = h->d.nx;
+    hd.ny = h->d.ny;
+    hd.q = h->q;
+    hd.precision = h->d.precision;
+    hd.patch = h->patch;
+    hd.main_prev_pre = h->main.prev_pre;
+    hd.fine_prev_pre = h->fine.prev_pre;
+    hd.bytes = lb_state_bytes(h);
+    char *o = (char *)d_out;
+    LB_TRY(h, hipMemcpyAsync(o, &hd, sizeof(hd), hipMemcpyHostToDevice, h->stream));
+    size_t off = 256;
+    const size_t mb = (size_t)h->q * h->main.pstride * h->ssize;
+    LB_TRY(h, hipMemcpyAsync(o + off, h->main.curp(), mb, hipMemcpyDeviceToDevice, h->stream));
+    LB_TRY(h, hipMemcpyAsync(o + off + mb, h->main.prevp(), mb, hipMemcpyDeviceToDevice, h->stream));
+    off += 2 * mb;
+    if (h->patch) {
+        const size_t fb = 5 * (size_t)h->fine.pstride * h->ssize;
+        LB_TRY(h, hipMemcpyAsync(o + off, h->fine.curp(), fb, hipMemcpyDeviceToDevice, h->stream));
+        LB_TRY(h, hipMemcpyAsync(o + off + fb, h->fine.prevp(), fb, hipMemcpyDeviceToDevice, h->stream));
+    }
+    LB_TRY(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_set_raw_state(lb_grid *h, const void *d_in) {
+    if (!h || !d_in) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    StateHeader hd;
+    LB_TRY(h, hipMemcpyAsync(&hd, d_in, sizeof(hd), hipMemcpyDeviceToHost, h->stream));
+    LB_TRY(h, hipStreamSynchronize(h->stream));
+    if (hd.magic != kStateMagic || hd.nx != h->d.nx || hd.ny != h->d.ny || hd.q != h->q ||
+        hd.precision != h->d.precision || hd.patch != (int32_t)h->patch || hd.bytes != lb_state_bytes(h))
+        return LB_E_INVALID;
+    const char *in = (const char *)d_in;
+    size_t off = 256;
+    const size_t mb = (size_t)h->q * h->main.pstride * h->ssize;
+    h->main.cur = 0;
+    LB_TRY(h, hipMemcpyAsync(h->main.pop[0], in + off, mb, hipMemcpyDeviceToDevice, h->stream));
+    LB_TRY(h, hipMemcpyAsync(h->main.pop[1], in + off + mb, mb, hipMemcpyDeviceToDevice, h->stream));
+    off += 2 * mb;
+    if (h->patch) {
+        const size_t fb = 5 * (size_t)h->fine.pstride * h->ssize;
+        h->fine.cur = 0;
+        LB_TRY(h, hipMemcpyAsync(h->fine.pop[0], in + off, fb, hipMemcpyDeviceToDevice, h->stream));
+        LB_TRY(h, hipMemcpyAsync(h->fine.pop[1], in + off + fb, fb, hipMemcpyDeviceToDevice, h->stream));
+    }
+    LB_TRY(h, hipStreamSynchronize(h->stream));
+    h->t = hd.t;
+    h->collided = hd.collided != 0;
+    h->main.prev_pre = hd.main_prev_pre;
+    h->fine.prev_pre = hd.fine_prev_pre;
+    return LB_OK;
+}
+
+int lb_sync(lb_grid *h) {
+    if (!h) return LB_E_INVALID;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) h->sticky = LB_E_HIP;
+    return h->sticky;
+}
+
+const char *lb_status_string(int code) {
+    switch (code) {
+    case LB_OK: return "ok";
+    case LB_E_INVALID: return "invalid argument";
+    case LB_E_RANGE: return "value out of range";
+    case LB_E_UNSUPPORTED: return "unsupported combination";
+    case LB_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case LB_E_HIP: return "HIP runtime error";
+    case LB_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+int lb_device_copy(void *d_dst, const void *d_src, size_t bytes, void *stream) {
+    if (!d_dst || !d_src) return LB_E_INVALID;
+    if (((uintptr_t)d_dst & 15u) || ((uintptr_t)d_src & 15u) || (bytes & 15u)) return LB_E_INVALID;
+    return lbw::launch_copy(d_dst, d_src, bytes, (hipStream_t)stream) == hipSuccess ? LB_OK : LB_E_HIP;
+}
+
+}  // extern "C"

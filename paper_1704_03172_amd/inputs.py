@@ -57,11 +57,13 @@ def random_fields(nx, ny, seed, amp=1e-3):
 # media
 # ---------------------------------------------------------------------------
 def _add_anomalies(c, n_anom, seed, margin, sig_lo, sig_hi, amp=0.1):
-    """c *= 1 + sum_k a_k exp(-|x - x_k|^2 / (2 s_k^2)), a_k ~ U[-amp, amp]."""
+    """c *= 1 + sum_k a_k exp(-|x - x_k|^2 / (2 s_k^2)), a_k ~ U[-amp, amp];
+    centres at least `margin` nodes (at most a quarter of the axis) inside."""
     ny, nx = c.shape
     rng = np.random.default_rng(seed)
-    xs = rng.uniform(margin, nx - margin, n_anom)
-    ys = rng.uniform(margin, ny - margin, n_anom)
+    mx, my = min(margin, nx / 4.0), min(margin, ny / 4.0)
+    xs = rng.uniform(mx, nx - mx, n_anom)
+    ys = rng.uniform(my, ny - my, n_anom)
     sg = rng.uniform(sig_lo, sig_hi, n_anom)
     aa = rng.uniform(-amp, amp, n_anom)
     bump = np.zeros_like(c)

@@ -1,0 +1,305 @@
+"""ctypes binding of liblbwave.so (C-ABI in include/lbwave.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory (the workspace, trace and field
+buffers) and the stream.  There is no CPU fallback: if the library is not
+built, importing the binding's entry points raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbwave.so")
+
+LB_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "value out of range",
+          -3: "unsupported combination", -4: "workspace", -5: "HIP runtime error",
+          -6: "call out of order"}
+F32, F64, F16S = 0, 1, 2
+PRECISION = {"f32": F32, "f64": F64, "f16s": F16S}
+FIELD = {"p": 1, "rho": 2, "jx": 4, "jy": 8}
+FIELD_ORDER = ("p", "rho", "jx", "jy")
+COLLISION = {"bgk": 0, "mrt": 1}
+
+# every symbol the header declares (the ABI test checks the export table)
+EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_workspace_bytes",
+           "lb_create_grid", "lb_destroy_grid", "lb_set_medium",
+           "lb_set_medium_fine", "lb_set_state", "lb_set_state_fine",
+           "lb_set_source", "lb_record", "lb_record_sum_rho", "lb_step_n",
+           "lb_get_time", "lb_get_field", "lb_get_field_fine",
+           "lb_state_bytes", "lb_get_state", "lb_set_raw_state", "lb_sync",
+           "lb_status_string", "lb_device_copy")
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("nbatch", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("s", ctypes.c_double * 9),
+        ("d2q9_ratio", ctypes.c_double),
+        ("sponge_width", ctypes.c_int32), ("_pad0", ctypes.c_int32),
+        ("sponge_sigma_max", ctypes.c_double),
+        ("patch_enable", ctypes.c_int32),
+        ("patch_x0", ctypes.c_int32), ("patch_y0", ctypes.c_int32),
+        ("patch_nx", ctypes.c_int32), ("patch_ny", ctypes.c_int32),
+        ("patch_refine", ctypes.c_int32),
+        ("patch_overlap_out", ctypes.c_int32), ("patch_overlap_in", ctypes.c_int32),
+        ("trace_capacity", ctypes.c_int64),
+        ("max_receivers", ctypes.c_int32), ("_pad1", ctypes.c_int32),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Load liblbwave.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbwave.so is not built (%s); run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    PD = ctypes.POINTER(Desc)
+    sig = {
+        "lb_default_desc": (None, [PD]),
+        "lb_validate_desc": (ctypes.c_int, [PD]),
+        "lb_workspace_bytes": (ctypes.c_size_t, [PD]),
+        "lb_create_grid": (ctypes.c_int, [PD, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "lb_destroy_grid": (ctypes.c_int, [vp]),
+        "lb_set_medium": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int]),
+        "lb_set_medium_fine": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int]),
+        "lb_set_state": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "lb_set_state_fine": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "lb_set_source": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i64]),
+        "lb_record": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, vp, u32]),
+        "lb_record_sum_rho": (ctypes.c_int, [vp, vp]),
+        "lb_step_n": (ctypes.c_int, [vp, i64]),
+        "lb_get_time": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+        "lb_get_field": (ctypes.c_int, [vp, u32, vp]),
+        "lb_get_field_fine": (ctypes.c_int, [vp, u32, vp]),
+        "lb_state_bytes": (ctypes.c_size_t, [vp]),
+        "lb_get_state": (ctypes.c_int, [vp, vp]),
+        "lb_set_raw_state": (ctypes.c_int, [vp, vp]),
+        "lb_sync": (ctypes.c_int, [vp]),
+        "lb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "lb_device_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(code, what):
+    if code != LB_OK:
+        raise LBError(code, what)
+
+
+def make_desc(nx, ny, lattice=5, collision="bgk", precision="f32", tau=0.5,
+              s=None, ratio=0.25, sponge_width=0, sponge_sigma_max=0.0,
+              patch=None, overlap_out=2, overlap_in=2, trace_capacity=0,
+              max_receivers=0):
+    d = Desc()
+    lib().lb_default_desc(ctypes.byref(d))
+    d.nx, d.ny = int(nx), int(ny)
+    d.lattice = int(lattice)
+    d.collision = COLLISION[collision]
+    d.precision = PRECISION[precision]
+    d.tau = float(tau)
+    if s is not None:
+        for k, v in enumerate(s):
+            d.s[k] = float(v)
+    d.d2q9_ratio = float(ratio)
+    d.sponge_width = int(sponge_width)
+    d.sponge_sigma_max = float(sponge_sigma_max)
+    if patch is not None:
+        d.patch_enable = 1
+        d.patch_x0, d.patch_y0, d.patch_nx, d.patch_ny = (int(v) for v in patch)
+        d.patch_overlap_out, d.patch_overlap_in = int(overlap_out), int(overlap_in)
+    d.trace_capacity = int(trace_capacity)
+    d.max_receivers = int(max_receivers)
+    return d
+
+
+def workspace_bytes(**kw):
+    d = make_desc(**kw)
+    return int(lib().lb_workspace_bytes(ctypes.byref(d)))
+
+
+def validate(**kw):
+    d = make_desc(**kw)
+    return int(lib().lb_validate_desc(ctypes.byref(d)))
+
+
+class Grid:
+    """One lattice (optionally with a refinement patch) on one HIP stream."""
+
+    def __init__(self, nx, ny, device=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.desc = make_desc(nx, ny, **kw)
+        self.nx, self.ny = int(nx), int(ny)
+        self.lattice = self.desc.lattice
+        self.precision = kw.get("precision", "f32")
+        self.dtype = torch.float64 if self.precision == "f64" else torch.float32
+        self.trace_capacity = int(kw.get("trace_capacity", 0))
+        L = lib()
+        nbytes = L.lb_workspace_bytes(ctypes.byref(self.desc))
+        if nbytes == 0:
+            _check(L.lb_validate_desc(ctypes.byref(self.desc)), "lb_validate_desc")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(L.lb_create_grid(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h)), "lb_create_grid")
+        self._h = h
+        self.traces = None
+        self.sum_rho = None
+        self.fine_shape = None
+        if self.desc.patch_enable:
+            W = self.desc.patch_nx + 2 * self.desc.patch_overlap_out
+            H = self.desc.patch_ny + 2 * self.desc.patch_overlap_out
+            self.fine_shape = (2 * H + 1, 2 * W + 1)
+
+    # ---- marshalling helpers ------------------------------------------------
+    def _arg(self, a, keep):
+        """(pointer, dtype code, on_device) for a numpy array or torch tensor."""
+        torch = self._torch
+        if a is None:
+            return None, F64, 0
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda:
+                if a.dtype not in (torch.float32, torch.float64):
+                    raise TypeError("device inputs must be float32 or float64")
+                a = a.contiguous()
+                keep.append(a)
+                return ctypes.c_void_p(a.data_ptr()), (F64 if a.dtype == torch.float64 else F32), 1
+            a = a.numpy()
+        arr = np.ascontiguousarray(a)
+        if arr.dtype not in (np.float32, np.float64):
+            arr = arr.astype(np.float64)
+        keep.append(arr)
+        return ctypes.c_void_p(arr.ctypes.data), (F64 if arr.dtype == np.float64 else F32), 0
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("grid is closed")
+        return self._h
+
+    # ---- C-ABI calls ----------------------------------------------------------
+    def set_medium(self, c2, fine=False):
+        keep = []
+        p, t, dev = self._arg(c2, keep)
+        fn = lib().lb_set_medium_fine if fine else lib().lb_set_medium
+        _check(fn(self.handle, p, t, dev), "lb_set_medium")
+
+    def set_state(self, rho, jx=None, jy=None, fine=False):
+        keep = []
+        pr, t, dev = self._arg(rho, keep)
+        px, tx, _ = self._arg(jx, keep)
+        py, ty, _ = self._arg(jy, keep)
+        if (jx is not None and tx != t) or (jy is not None and ty != t):
+            raise TypeError("rho, jx, jy must share one dtype")
+        fn = lib().lb_set_state_fine if fine else lib().lb_set_state
+        _check(fn(self.handle, pr, px, py, t, dev), "lb_set_state")
+
+    def set_source(self, x, y, wavelet):
+        w = np.ascontiguousarray(wavelet, dtype=np.float64)
+        _check(lib().lb_set_source(self.handle, int(x), int(y),
+                                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(w.size)),
+               "lb_set_source")
+
+    def record(self, receivers, fields=("p",)):
+        """Register receivers (int array (nrec, 2) of (x, y)); returns the
+        device trace tensor [nfields][nrec][trace_capacity]."""
+        torch = self._torch
+        rec = np.ascontiguousarray(receivers, dtype=np.int32).reshape(-1, 2)
+        nrec = rec.shape[0]
+        if nrec == 0:
+            _check(lib().lb_record(self.handle, None, 0, None, 0), "lb_record")
+            self.traces = None
+            return None
+        what = 0
+        for f in fields:
+            what |= FIELD[f]
+        nf = bin(what).count("1")
+        self.traces = torch.zeros((nf, nrec, self.trace_capacity), dtype=self.dtype, device=self.device)
+        self.trace_fields = tuple(f for f in FIELD_ORDER if what & FIELD[f])
+        _check(lib().lb_record(self.handle, rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nrec,
+                               ctypes.c_void_p(self.traces.data_ptr()), what), "lb_record")
+        return self.traces
+
+    def record_sum_rho(self):
+        torch = self._torch
+        self.sum_rho = torch.zeros(self.trace_capacity, dtype=torch.float64, device=self.device)
+        _check(lib().lb_record_sum_rho(self.handle, ctypes.c_void_p(self.sum_rho.data_ptr())),
+               "lb_record_sum_rho")
+        return self.sum_rho
+
+    def step(self, n=1):
+        _check(lib().lb_step_n(self.handle, int(n)), "lb_step_n")
+
+    @property
+    def time(self):
+        t = ctypes.c_int64()
+        _check(lib().lb_get_time(self.handle, ctypes.byref(t)), "lb_get_time")
+        return int(t.value)
+
+    def field(self, what="rho", fine=False):
+        torch = self._torch
+        shape = self.fine_shape if fine else (self.ny, self.nx)
+        out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        fn = lib().lb_get_field_fine if fine else lib().lb_get_field
+        _check(fn(self.handle, FIELD[what], ctypes.c_void_p(out.data_ptr())), "lb_get_field")
+        return out
+
+    def get_state(self):
+        torch = self._torch
+        n = lib().lb_state_bytes(self.handle)
+        out = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        _check(lib().lb_get_state(self.handle, ctypes.c_void_p(out.data_ptr())), "lb_get_state")
+        return out
+
+    def set_raw_state(self, blob):
+        _check(lib().lb_set_raw_state(self.handle, ctypes.c_void_p(blob.data_ptr())), "lb_set_raw_state")
+
+    def sync(self):
+        _check(lib().lb_sync(self.handle), "lb_sync")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            code = lib().lb_destroy_grid(self._h)
+            self._h = None
+            _check(code, "lb_destroy_grid")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_copy(dst, src, nbytes, stream=None):
+    """The library's plain 16-byte vector copy kernel (bandwidth reference)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().lb_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(s.cuda_stream)),
+           "lb_device_copy")

@@ -1,0 +1,136 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/lbwave.h declares, and validates descriptors and arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "lbwave.h")
+
+
+@pytest.fixture(scope="module")
+def lw():
+    from paper_1704_03172_amd import lbwave
+    if not os.path.exists(lbwave.LIB_PATH):
+        from paper_1704_03172_amd import build
+        build.build()
+    lbwave.lib()
+    return lbwave
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported(lw):
+    names = _declared_functions()
+    assert len(names) >= 20
+    L = lw.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lw.EXPORTS) == names
+
+
+def test_desc_layout_matches_c(lw):
+    # lb_default_desc writes exactly sizeof(lb_grid_desc) bytes; a sentinel
+    # after the ctypes struct must survive and the fields must read back.
+    class Padded(ctypes.Structure):
+        _fields_ = [("d", lw.Desc), ("tail", ctypes.c_uint8 * 64)]
+    p = Padded()
+    for i in range(64):
+        p.tail[i] = 0xAB
+    lw.lib().lb_default_desc(ctypes.byref(p.d))
+    assert all(b == 0xAB for b in p.tail)
+    d = p.d
+    assert (d.nx, d.ny, d.lattice, d.collision, d.precision, d.nbatch) == (64, 64, 5, 0, 0, 1)
+    assert d.tau == 0.5 and list(d.s) == [1, 1, 1, 2, 2, 2, 1, 1, 2]
+    assert d.d2q9_ratio == 0.25 and d.sponge_width == 0 and d.sponge_sigma_max == 0.0
+    assert (d.patch_enable, d.patch_refine, d.patch_overlap_out, d.patch_overlap_in) == (0, 2, 2, 2)
+    assert d.trace_capacity == 0 and d.max_receivers == 0
+    assert ctypes.sizeof(lw.Desc) == 176
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), 0),
+    (dict(lattice=7), -1),
+    (dict(nx=0), -2),
+    (dict(ny=70000), -2),
+    (dict(tau=0.49), -2),
+    (dict(collision="mrt", s=[1, 1, 1, 2.5, 2]), -2),
+    (dict(collision="mrt", s=[1, 1, 1, 0.0, 2]), -2),
+    (dict(collision="mrt", s=[0, 0, 0, 2, 2]), 0),           # conserved rates ignored
+    (dict(lattice=9, ratio=-0.1), -2),
+    (dict(sponge_width=-1), -2),
+    (dict(sponge_sigma_max=1.5), -2),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64)), 0),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64), tau=0.6), -3),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64), lattice=9), -3),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64), collision="mrt", s=[1, 1, 1, 2, 2]), 0),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64), collision="mrt", s=[1, 1, 1, 1.9, 2]), -3),
+    (dict(nx=256, ny=256, patch=(2, 96, 64, 64)), -2),
+    (dict(nx=256, ny=256, patch=(96, 96, 64, 64), sponge_width=100), -2),
+    (dict(nx=256, ny=256, patch=(96, 96, 4, 64)), -2),
+])
+def test_validate(lw, kw, code):
+    args = dict(nx=64, ny=64)
+    args.update(kw)
+    assert lw.validate(**args) == code
+    nb = lw.workspace_bytes(**args)
+    assert (nb > 0) == (code == 0)
+
+
+def test_workspace_accounting(lw):
+    # two population buffers dominate: 2 * Q * N * sizeof(storage)
+    for prec, sz in (("f32", 4), ("f64", 8), ("f16s", 2)):
+        for q in (5, 9):
+            nb = lw.workspace_bytes(nx=1024, ny=512, lattice=q, precision=prec)
+            pops = 2 * q * 1024 * 512 * sz
+            c2 = 1024 * 512 * (8 if prec == "f64" else 4)
+            assert pops + c2 <= nb <= pops + c2 + 4 * 1024 * 1024
+
+
+def test_create_rejects_bad_workspace_before_touching_gpu(lw):
+    d = lw.make_desc(64, 64)
+    h = ctypes.c_void_p()
+    L = lw.lib()
+    assert L.lb_create_grid(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == -4
+    assert L.lb_create_grid(ctypes.byref(d), ctypes.c_void_p(256), 16, None, ctypes.byref(h)) == -4
+    assert L.lb_create_grid(ctypes.byref(d), ctypes.c_void_p(257), 1 << 30, None, ctypes.byref(h)) == -4
+    bad = lw.make_desc(64, 64, tau=0.1)
+    assert L.lb_create_grid(ctypes.byref(bad), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) == -2
+    assert not h.value
+
+
+def test_null_handles(lw):
+    L = lw.lib()
+    assert L.lb_destroy_grid(None) == 0
+    assert L.lb_step_n(None, 1) == -1
+    assert L.lb_sync(None) == -1
+    assert L.lb_set_medium(None, None, 0, 0) == -1
+    t = ctypes.c_int64()
+    assert L.lb_get_time(None, ctypes.byref(t)) == -1
+    assert L.lb_state_bytes(None) == 0
+    assert L.lb_device_copy(None, None, 16, None) == -1
+    assert L.lb_device_copy(ctypes.c_void_p(256), ctypes.c_void_p(272), 15, None) == -1
+
+
+def test_status_strings(lw):
+    L = lw.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = L.lb_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert L.lb_status_string(17).decode() == "unknown status"
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    from paper_1704_03172_amd import lbwave
+    monkeypatch.setattr(lbwave, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(lbwave, "_LIB", None)
+    with pytest.raises(RuntimeError):
+        lbwave.lib()
