@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -203,6 +205,22 @@ def main():
         g.close()
         del g
 
+    serving = None
+    if not args.no_serving:
+        from paper_1704_03172_amd import serve
+        trace = inputs.serving_trace(args.serve_requests, 50.0, seed=4)
+        serving = {"requests": args.serve_requests, "rate_per_s": 50.0, "seed": 4}
+        for policy in ("fifo", "sjf"):
+            log("serving %d requests at 50/s, continuous batching (%s admission)" % (args.serve_requests, policy))
+            srv = serve.ShotServer(64 << 30, 32, None, policy=policy)
+            _, serving["batched_" + policy] = srv.run(trace)
+            srv.close()
+            del srv
+            torch.cuda.empty_cache()
+        log("serving the same trace one shot per launch (FIFO)")
+        _, serving["one_shot_per_launch"] = serve.run_fifo(trace)
+        torch.cuda.empty_cache()
+
     traffic = measured_traffic() if args.n == 4096 else None
     cpu = None
     if not args.no_cpu:
@@ -229,6 +247,7 @@ def main():
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "traces_finite": finite,
         "variants": variants,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -219,6 +219,76 @@ int lb_sync(lb_grid *h);
 /* Static description of a status code. */
 const char *lb_status_string(int code);
 
+/* ---- batched executor (serving many shots at once) --------------------
+ *
+ * Many independent shots (grids of different sizes, each with its own medium,
+ * source, receivers and step count) advance together: one launch per time
+ * step covers the tiles of every active shot, and the shot's time and buffer
+ * parity live in device memory, so a tick of k steps is captured once as a
+ * HIP graph and replayed until the set of shots changes.  Each shot computes
+ * exactly what an lb_grid with the same parameters computes (same per-node
+ * update), bitwise, whatever its batch mates.  Shots start at rest.  With
+ * graphs on, a fixed block of steps is captured per set of active shots and
+ * replayed as often as a tick needs.
+ */
+typedef struct lb_batch lb_batch;
+
+typedef struct {
+    int32_t nx, ny;           /* shot grid, as lb_grid_desc                 */
+    int32_t src_x, src_y;     /* source node                                */
+    int64_t nsteps;           /* times 0..nsteps are computed and recorded  */
+    int32_t sponge_width;     /* as lb_grid_desc                            */
+    int32_t nrec;             /* receivers (traces of p only)               */
+    double sponge_sigma_max;
+} lb_shot_desc;
+
+/* Device bytes of a batch with up to max_shots concurrent shots. */
+size_t lb_batch_workspace_bytes(int32_t max_shots);
+
+/* Create a batch executor.  `scheme` supplies lattice, collision, precision,
+ * tau, s and d2q9_ratio (its grid, sponge, patch and capacity fields are
+ * ignored; no patch).  use_graph = 1 captures ticks as HIP graphs (needs a
+ * stream other than the legacy default stream), 0 launches them directly. */
+int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots,
+                    void *d_workspace, size_t ws_bytes, void *stream,
+                    int use_graph, lb_batch **out);
+
+/* Device bytes one shot needs: two population buffers, c^2, the wavelet
+ * (nsteps + 1 doubles) and its receiver tables.  The footprint used for
+ * admission; the trace buffer [nrec][nsteps + 1] is the caller's. 0 if the
+ * shot description is invalid. */
+size_t lb_shot_workspace_bytes(const lb_batch *b, const lb_shot_desc *s);
+
+/* Admit a shot into a free slot: c2 [ny][nx] as for lb_set_medium (range
+ * checked), wavelet S(n) for n < nt (host, copied), receivers rxy[nrec][2]
+ * (host, copied), caller-owned device traces [nrec][nsteps + 1] of the
+ * arithmetic type receiving p at every time.  Zeroes the state, performs
+ * the collision of time 0 and records time 0.  *slot receives the slot
+ * index.  LB_E_RANGE if no slot is free.  Synchronises the stream. */
+int lb_batch_add_shot(lb_batch *b, const lb_shot_desc *s, void *d_ws,
+                      size_t ws_bytes, const void *c2, lb_dtype t,
+                      int on_device, const double *wavelet, int64_t nt,
+                      const int32_t *rxy, void *d_traces, int32_t *slot);
+
+/* Retire a shot (finished or not) and free its slot; after the call the
+ * library no longer touches the shot's workspace or traces.  Synchronises
+ * the stream. */
+int lb_batch_remove_shot(lb_batch *b, int32_t slot);
+
+/* Enqueue k time steps for every active shot; shots that reach their last
+ * time stop updating inside the tick.  Returns without waiting. */
+int lb_batch_tick(lb_batch *b, int64_t k);
+
+/* Time reached by every slot (host array of max_shots; -1 for free slots).
+ * Synchronises the stream. */
+int lb_batch_times(lb_batch *b, int64_t *t_out);
+
+/* Wait for all enqueued work; returns the sticky error. */
+int lb_batch_sync(lb_batch *b);
+
+/* Release the executor (not the workspaces).  NULL-safe. */
+int lb_batch_destroy(lb_batch *b);
+
 /* Plain device copy of `bytes` bytes (16-byte nontemporal vector loads and
  * stores) on a stream: the measured reference for attainable HBM bandwidth.
  * Both pointers 16-byte aligned, bytes a multiple of 16. */

@@ -102,7 +102,44 @@ struct FieldParams {
     void *out = nullptr;
 };
 
+// One shot of the batched executor (serving).  Static description, written
+// by the host when the shot is admitted.
+struct ShotEntry {
+    void *pop0 = nullptr, *pop1 = nullptr;   // population buffers A / B
+    const void *c2 = nullptr;
+    const double *wavelet = nullptr;         // S(n), n < wavelet_len
+    int64_t wavelet_len = 0;
+    Receivers rec;                           // col is set per launch
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;
+    int32_t sponge_width = 0;
+    double sponge_smax = 0.0;
+    int32_t src_x = -1, src_y = -1;
+    int32_t bx = 0;                          // step blocks per row
+};
+
+// Dynamic state of a shot, advanced on the device.
+struct ShotState {
+    int64_t t = 0;                           // time of the newest state
+    int64_t t_end = 0;                       // last time to compute
+    int32_t cur = 0;                         // buffer holding h(t): 0 = A
+    int32_t active = 0;
+};
+
+struct BatchParams {
+    const ShotEntry *table = nullptr;        // [max_shots]
+    ShotState *state = nullptr;              // [max_shots]
+    const int64_t *prefix = nullptr;         // [nact + 1] first block of each active shot
+    const int32_t *order = nullptr;          // [nact] slot of each active shot
+    int32_t nact = 0;
+    Collision coll;
+};
+
 // Launchers (lb_kernels.hip).  All return the launch status.
+int step_vwidth(int storage);
+int step_tile_nodes(int storage);   // x-nodes covered by one step block
+hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s);
+hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);

@@ -207,94 +207,101 @@ __device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, 
 }
 
 // ---- fused step -------------------------------------------------------------
+// One thread's share of the update: V consecutive nodes (x0 .. x0+V-1) of row
+// y.  Returns the FP64 sum of rho over them when p.partial is set.
+template <typename S, int Q, int KIND, bool PULL>
+__device__ inline double update_tile(const StepParams &p, int x0, int y) {
+    using T = typename Tr<S>::T;
+    constexpr int V = PULL ? Tr<S>::V : 1;
+    const int nx = p.nx, ny = p.ny;
+    double local = 0.0;
+    if (x0 >= nx) return local;
+
+    const S *src = reinterpret_cast<const S *>(p.src);
+    T g[Q][V];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = PULL ? wrapi(y - cyv<Q>(i), ny) : y;
+        const S *row = src + i * p.pstride + (int64_t)ys * nx;
+        S t[V];
+        load_x<S, V>(row, PULL ? x0 - cxv<Q>(i) : x0, nx, t);
+#pragma unroll
+        for (int j = 0; j < V; ++j) g[i][j] = T(t[j]);
+    }
+    T c2v[V];
+    {
+        const T *c2row = reinterpret_cast<const T *>(p.c2) + (int64_t)y * nx;
+        if (V > 1 && x0 + V <= nx) {
+            typedef T ct __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+            ct t = __builtin_nontemporal_load(reinterpret_cast<const ct *>(c2row + x0));
+#pragma unroll
+            for (int j = 0; j < V; ++j) c2v[j] = t[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) c2v[j] = c2row[min(x0 + j, nx - 1)];
+        }
+    }
+
+    // receivers of this row (CSR lookup; rows without receivers cost one
+    // uniform pair of loads)
+    int rb = 0, re = 0;
+    if (p.rec.row_ptr) {
+        rb = p.rec.row_ptr[y];
+        re = p.rec.row_ptr[y + 1];
+    }
+
+    S outv[Q][V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        T gj[Q], gs[Q], w[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+        const int x = x0 + j;
+        if (rb < re && x < nx) {
+            T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                rho += gj[i];
+                jx += T(cxv<Q>(i)) * gj[i];
+                jy += T(cyv<Q>(i)) * gj[i];
+            }
+            int lo = rb, hi = re;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
+            }
+            for (; lo < re && p.rec.xs[lo] == x; ++lo)
+                write_fields<T>(p.rec, p.rec.slot[lo], rho, jx, jy, c2v[j]);
+        }
+        if (p.partial && x < nx) {
+            T rho = T(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) rho += gj[i];
+            local += double(rho);
+        }
+        collide<T, Q, KIND>(gj, c2v[j], p.coll, gs, w);
+        if (y == p.src_y && x == p.src_x) {
+            const T sn = T(p.s_n);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+        }
+        const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) outv[i][j] = S(gs[i] * sf);
+    }
+    S *dst = reinterpret_cast<S *>(p.dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        store_x<S, V>(dst + i * p.pstride + (int64_t)y * nx, x0, nx, outv[i]);
+    return local;
+}
+
 template <typename S, int Q, int KIND, bool PULL>
 __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
-    using T = typename Tr<S>::T;
     constexpr int V = PULL ? Tr<S>::V : 1;
     const int y = blockIdx.y;
     const int x0 = (blockIdx.x * kStepBlock + threadIdx.x) * V;
-    const int nx = p.nx, ny = p.ny;
-    const bool active = x0 < nx;
-    double local = 0.0;
-
-    if (active) {
-        const S *src = reinterpret_cast<const S *>(p.src);
-        T g[Q][V];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int ys = PULL ? wrapi(y - cyv<Q>(i), ny) : y;
-            const S *row = src + i * p.pstride + (int64_t)ys * nx;
-            S t[V];
-            load_x<S, V>(row, PULL ? x0 - cxv<Q>(i) : x0, nx, t);
-#pragma unroll
-            for (int j = 0; j < V; ++j) g[i][j] = T(t[j]);
-        }
-        T c2v[V];
-        {
-            const T *c2row = reinterpret_cast<const T *>(p.c2) + (int64_t)y * nx;
-            if (V > 1 && x0 + V <= nx) {
-                typedef T ct __attribute__((ext_vector_type(V), aligned(sizeof(T))));
-                ct t = __builtin_nontemporal_load(reinterpret_cast<const ct *>(c2row + x0));
-#pragma unroll
-                for (int j = 0; j < V; ++j) c2v[j] = t[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < V; ++j) c2v[j] = c2row[min(x0 + j, nx - 1)];
-            }
-        }
-
-        // receivers of this row (CSR lookup; rows without receivers cost one
-        // uniform pair of loads)
-        int rb = 0, re = 0;
-        if (p.rec.row_ptr) {
-            rb = p.rec.row_ptr[y];
-            re = p.rec.row_ptr[y + 1];
-        }
-
-        S outv[Q][V];
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            T gj[Q], gs[Q], w[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
-            const int x = x0 + j;
-            if (rb < re && x < nx) {
-                T rho = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    rho += gj[i];
-                    jx += T(cxv<Q>(i)) * gj[i];
-                    jy += T(cyv<Q>(i)) * gj[i];
-                }
-                int lo = rb, hi = re;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
-                }
-                for (; lo < re && p.rec.xs[lo] == x; ++lo)
-                    write_fields<T>(p.rec, p.rec.slot[lo], rho, jx, jy, c2v[j]);
-            }
-            if (p.partial && x < nx) {
-                T rho = T(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) rho += gj[i];
-                local += double(rho);
-            }
-            collide<T, Q, KIND>(gj, c2v[j], p.coll, gs, w);
-            if (y == p.src_y && x == p.src_x) {
-                const T sn = T(p.s_n);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
-            }
-            const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) outv[i][j] = S(gs[i] * sf);
-        }
-        S *dst = reinterpret_cast<S *>(p.dst);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            store_x<S, V>(dst + i * p.pstride + (int64_t)y * nx, x0, nx, outv[i]);
-    }
+    double local = update_tile<S, Q, KIND, PULL>(p, x0, y);
 
     if (p.partial) {   // uniform branch: per-block sum of rho in FP64
         for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
@@ -307,6 +314,61 @@ __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
             for (int k = 0; k < kStepBlock / 64; ++k) s += sh[k];
             p.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
         }
+    }
+}
+
+// ---- batched step over many shots (serving) ------------------------------------
+// One launch covers every active shot: block b belongs to the shot whose
+// block range [prefix[a], prefix[a+1]) holds it; the shot's time and buffer
+// parity live in device memory, so the same launch sequence can be captured
+// once and replayed.  The per-node update is update_tile(), identical to the
+// single-grid step, so a shot's results do not depend on its batch mates.
+template <typename S, int Q, int KIND>
+__global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
+    constexpr int V = Tr<S>::V;
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = bp.nact - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bp.prefix[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const int slot = bp.order[lo];
+    const ShotState ss = bp.state[slot];
+    if (!ss.active || ss.t >= ss.t_end) return;
+    const ShotEntry &e = bp.table[slot];
+    const int64_t local = b - bp.prefix[lo];
+    const int y = int(local / e.bx);
+    const int tile = int(local % e.bx);
+    StepParams p;
+    p.src = ss.cur ? e.pop1 : e.pop0;
+    p.dst = ss.cur ? e.pop0 : e.pop1;
+    p.c2 = e.c2;
+    p.nx = e.nx;
+    p.ny = e.ny;
+    p.pstride = e.pstride;
+    p.q = Q;
+    p.coll = bp.coll;
+    p.sponge_width = e.sponge_width;
+    p.sponge_smax = e.sponge_smax;
+    p.src_x = e.src_x;
+    p.src_y = e.src_y;
+    const int64_t tn = ss.t + 1;
+    p.s_n = tn < e.wavelet_len ? e.wavelet[tn] : 0.0;
+    p.rec = e.rec;
+    p.rec.col = tn;
+    p.partial = nullptr;
+    update_tile<S, Q, KIND, true>(p, (tile * kStepBlock + threadIdx.x) * V, y);
+}
+
+// After a batched step: every active, unfinished shot moves to the next time
+// and swaps its buffers.
+__global__ __launch_bounds__(kBlock) void k_batch_advance(ShotState *state, const int32_t *order, int nact) {
+    int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nact) return;
+    ShotState &ss = state[order[a]];
+    if (ss.active && ss.t < ss.t_end) {
+        ss.t += 1;
+        ss.cur ^= 1;
     }
 }
 
@@ -593,6 +655,34 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull, hipStream_t 
     case ST_F16: return step_dispatch<_Float16>(p, pull, s);
     }
     return hipErrorInvalidValue;
+}
+
+int step_vwidth(int storage) {
+    return storage == ST_F32 ? Tr<float>::V : storage == ST_F64 ? Tr<double>::V : Tr<_Float16>::V;
+}
+
+int step_tile_nodes(int storage) { return step_vwidth(storage) * kStepBlock; }
+
+hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s) {
+    if (nblocks <= 0 || bp.nact <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblocks);
+    const bool mrt = bp.coll.kind == 1;
+#define LBW_B(SS, QQ)                                                                              \
+    do {                                                                                           \
+        if (mrt) hipLaunchKernelGGL((k_step_batch<SS, QQ, 1>), grid, dim3(kStepBlock), 0, s, bp);  \
+        else hipLaunchKernelGGL((k_step_batch<SS, QQ, 0>), grid, dim3(kStepBlock), 0, s, bp);      \
+    } while (0)
+    if (storage == ST_F32) { if (q == 5) LBW_B(float, 5); else LBW_B(float, 9); }
+    else if (storage == ST_F64) { if (q == 5) LBW_B(double, 5); else LBW_B(double, 9); }
+    else { if (q == 5) LBW_B(_Float16, 5); else LBW_B(_Float16, 9); }
+#undef LBW_B
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact, hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_advance, dim3(blocks_for(nact)), dim3(kBlock), 0, s, state, order, nact);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks, double *out, hipStream_t s) {

@@ -4,6 +4,7 @@
 // schedule (arXiv:1704.03172, Sec. IV).  The library never allocates device
 // memory; everything lives in the caller's workspace.
 #include "lbwave.h"
+#include "lb_host.h"
 #include "lb_internal.h"
 
 #include <algorithm>
@@ -22,21 +23,12 @@ using lbw::StepParams;
 
 constexpr uint64_t kStateMagic = 0x4c42574156453031ull;  // "LBWAVE01"
 
-size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+using lbw::align_up;
+using lbw::compute_bytes;
+using lbw::storage_bytes;
+using lbw::storage_kind;
 
-size_t storage_bytes(int p) { return p == LB_F64 ? 8 : (p == LB_F16S ? 2 : 4); }
-size_t compute_bytes(int p) { return p == LB_F64 ? 8 : 4; }
-int storage_kind(int p) { return p == LB_F64 ? lbw::ST_F64 : (p == LB_F16S ? lbw::ST_F16 : lbw::ST_F32); }
-
-// Row norms |M_k|^2 of the moment matrices of Appendix A.
-const double kNormD2Q5[5] = {5, 2, 2, 20, 4};
-const double kNormD2Q9[9] = {9, 6, 6, 36, 4, 36, 12, 12, 4};
-
-double c2_max(const lb_grid_desc *d) {
-    if (d->lattice == LB_D2Q5) return 0.5;
-    const double r = d->d2q9_ratio;
-    return (1.0 + 2.0 * r) / (2.0 + 2.0 * r);
-}
+double c2_max(const lb_grid_desc *d) { return lbw::c2_max(d->lattice, d->d2q9_ratio); }
 
 bool omega_is_two(const lb_grid_desc *d) {
     if (d->collision == LB_BGK) return d->tau == 0.5;
@@ -64,18 +56,10 @@ PatchGeom patch_geom(const lb_grid_desc *d) {
 
 int validate(const lb_grid_desc *d) {
     if (!d) return LB_E_INVALID;
-    if (d->lattice != LB_D2Q5 && d->lattice != LB_D2Q9) return LB_E_INVALID;
-    if (d->collision != LB_BGK && d->collision != LB_MRT) return LB_E_INVALID;
-    if (d->precision != LB_F32 && d->precision != LB_F64 && d->precision != LB_F16S) return LB_E_INVALID;
+    int rc = lbw::validate_scheme(d);
+    if (rc) return rc;
     if (d->nx < 1 || d->ny < 1 || d->ny > 65535 || d->nx > (1 << 24)) return LB_E_RANGE;
     if (d->nbatch != 1) return LB_E_UNSUPPORTED;
-    if (d->collision == LB_BGK) {
-        if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return LB_E_RANGE;
-    } else {
-        for (int k = 3; k < d->lattice; ++k)
-            if (!(d->s[k] > 0.0 && d->s[k] <= 2.0)) return LB_E_RANGE;
-    }
-    if (d->lattice == LB_D2Q9 && !(d->d2q9_ratio >= 0.0 && std::isfinite(d->d2q9_ratio))) return LB_E_RANGE;
     if (d->sponge_width < 0 || !(d->sponge_sigma_max >= 0.0 && d->sponge_sigma_max <= 1.0)) return LB_E_RANGE;
     if (d->trace_capacity < 0 || d->max_receivers < 0) return LB_E_RANGE;
     if (d->patch_enable) {
@@ -110,7 +94,7 @@ Layout make_layout(const lb_grid_desc *d) {
     // population stride: 256-element aligned, skewed by 1024 elements so
     // that the population arrays of power-of-two grids do not alias in the
     // low address bits
-    L.pstride = (int64_t)align_up((size_t)n + 1024, 256);
+    L.pstride = lbw::population_stride(n);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.pop[0] = take((size_t)d->lattice * L.pstride * ss);
@@ -126,7 +110,7 @@ Layout make_layout(const lb_grid_desc *d) {
     if (d->patch_enable) {
         PatchGeom g = patch_geom(d);
         const int64_t nf = (int64_t)g.nxf * g.nyf;
-        L.fpstride = (int64_t)align_up((size_t)nf + 1024, 256);
+        L.fpstride = lbw::population_stride(nf);
         L.fpop[0] = take(5 * (size_t)L.fpstride * ss);
         L.fpop[1] = take(5 * (size_t)L.fpstride * ss);
         L.fc2 = take((size_t)nf * ts);
@@ -356,38 +340,11 @@ int set_medium_impl(lb_grid *h, Lattice &g, const void *c2, lb_dtype t, int on_d
     if (!h || !c2) return LB_E_INVALID;
     if (h->sticky) return h->sticky;
     if (t != LB_F32 && t != LB_F64) return LB_E_INVALID;
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const double cmax = c2_max(&h->d);
     g.medium = false;
-    if (!on_device) {
-        const bool in64 = t == LB_F64;
-        if (h->tsize == 8) {
-            std::vector<double> v((size_t)n);
-            for (int64_t k = 0; k < n; ++k) {
-                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
-                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
-                v[(size_t)k] = x;
-            }
-            int rc = upload_sync(h, g.c2, v.data(), (size_t)n * 8);
-            if (rc) return rc;
-        } else {
-            std::vector<float> v((size_t)n);
-            for (int64_t k = 0; k < n; ++k) {
-                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
-                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
-                v[(size_t)k] = (float)x;
-            }
-            int rc = upload_sync(h, g.c2, v.data(), (size_t)n * 4);
-            if (rc) return rc;
-        }
-    } else {
-        LB_TRY(h, lbw::launch_fill_zero(h->scratch, 256, h->stream));
-        LB_TRY(h, lbw::launch_convert_c2(h->storage, c2, t == LB_F64, g.c2, n, cmax, h->scratch, h->stream));
-        int32_t bad = 0;
-        LB_TRY(h, hipMemcpyAsync(&bad, h->scratch, 4, hipMemcpyDeviceToHost, h->stream));
-        LB_TRY(h, hipStreamSynchronize(h->stream));
-        if (bad) return LB_E_RANGE;
-    }
+    int rc = lbw::upload_c2(h->stream, h->d.precision, h->d.lattice, h->d.d2q9_ratio, g.c2, c2, t, on_device,
+                            (int64_t)g.nx * g.ny, h->scratch);
+    if (rc == LB_E_HIP) h->sticky = LB_E_HIP;
+    if (rc) return rc;
     g.medium = true;
     return LB_OK;
 }
@@ -566,14 +523,7 @@ int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes, vo
     h->q = d->lattice;
     h->L = L;
     h->ws = (char *)d_workspace;
-    Collision &c = h->coll;
-    c.kind = d->collision;
-    c.omega = 1.0 / d->tau;
-    const double *norm = d->lattice == LB_D2Q5 ? kNormD2Q5 : kNormD2Q9;
-    for (int k = 0; k < 9; ++k) c.srate[k] = (k >= 3 && k < d->lattice) ? d->s[k] / norm[k] : 0.0;
-    c.ratio = d->lattice == LB_D2Q9 ? d->d2q9_ratio : 0.0;
-    c.kax = d->lattice == LB_D2Q9 ? 1.0 / (2.0 + 4.0 * c.ratio) : 0.5;
-    c.kdg = d->lattice == LB_D2Q9 ? c.ratio / (2.0 + 4.0 * c.ratio) : 0.0;
+    h->coll = lbw::make_collision(d);
 
     Lattice &m = h->main;
     m.nx = d->nx;
@@ -836,3 +786,71 @@ int lb_device_copy(void *d_dst, const void *d_src, size_t bytes, void *stream) {
 }
 
 }  // extern "C"
+
+namespace lbw {
+
+// Row norms |M_k|^2 of the moment matrices of Appendix A.
+static const double kNormD2Q5[5] = {5, 2, 2, 20, 4};
+static const double kNormD2Q9[9] = {9, 6, 6, 36, 4, 36, 12, 12, 4};
+
+Collision make_collision(const lb_grid_desc *d) {
+    Collision c;
+    c.kind = d->collision;
+    c.omega = 1.0 / d->tau;
+    const double *norm = d->lattice == LB_D2Q5 ? kNormD2Q5 : kNormD2Q9;
+    for (int k = 0; k < 9; ++k) c.srate[k] = (k >= 3 && k < d->lattice) ? d->s[k] / norm[k] : 0.0;
+    c.ratio = d->lattice == LB_D2Q9 ? d->d2q9_ratio : 0.0;
+    c.kax = d->lattice == LB_D2Q9 ? 1.0 / (2.0 + 4.0 * c.ratio) : 0.5;
+    c.kdg = d->lattice == LB_D2Q9 ? c.ratio / (2.0 + 4.0 * c.ratio) : 0.0;
+    return c;
+}
+
+int validate_scheme(const lb_grid_desc *d) {
+    if (d->lattice != LB_D2Q5 && d->lattice != LB_D2Q9) return LB_E_INVALID;
+    if (d->collision != LB_BGK && d->collision != LB_MRT) return LB_E_INVALID;
+    if (d->precision != LB_F32 && d->precision != LB_F64 && d->precision != LB_F16S) return LB_E_INVALID;
+    if (d->collision == LB_BGK) {
+        if (!(d->tau >= 0.5) || !std::isfinite(d->tau)) return LB_E_RANGE;
+    } else {
+        for (int k = 3; k < d->lattice; ++k)
+            if (!(d->s[k] > 0.0 && d->s[k] <= 2.0)) return LB_E_RANGE;
+    }
+    if (d->lattice == LB_D2Q9 && !(d->d2q9_ratio >= 0.0 && std::isfinite(d->d2q9_ratio))) return LB_E_RANGE;
+    return LB_OK;
+}
+
+int upload_c2(hipStream_t s, int precision, int lattice, double ratio, void *dst, const void *c2, lb_dtype t,
+              int on_device, int64_t n, int32_t *scratch) {
+    const double cmax = lbw::c2_max(lattice, ratio);
+    const bool in64 = t == LB_F64;
+    if (!on_device) {
+        if (compute_bytes(precision) == 8) {
+            std::vector<double> v((size_t)n);
+            for (int64_t k = 0; k < n; ++k) {
+                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
+                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
+                v[(size_t)k] = x;
+            }
+            if (hipMemcpyAsync(dst, v.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess) return LB_E_HIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return LB_E_HIP;
+        } else {
+            std::vector<float> v((size_t)n);
+            for (int64_t k = 0; k < n; ++k) {
+                double x = in64 ? ((const double *)c2)[k] : (double)((const float *)c2)[k];
+                if (!(x > 0.0 && x <= cmax)) return LB_E_RANGE;
+                v[(size_t)k] = (float)x;
+            }
+            if (hipMemcpyAsync(dst, v.data(), (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess) return LB_E_HIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return LB_E_HIP;
+        }
+        return LB_OK;
+    }
+    if (launch_fill_zero(scratch, 256, s) != hipSuccess) return LB_E_HIP;
+    if (launch_convert_c2(storage_kind(precision), c2, in64, dst, n, cmax, scratch, s) != hipSuccess) return LB_E_HIP;
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, scratch, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return LB_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return LB_E_HIP;
+    return bad ? LB_E_RANGE : LB_OK;
+}
+
+}  // namespace lbw

@@ -168,3 +168,82 @@ def refined_workload(n=2048, nsteps=3000, nrec=128, lens_speed=0.25,
         "wavelet": ricker_wavelet(nsteps + 1, fc),
         "receivers": surface_receivers(n, nrec, depth, L),
     }
+
+
+# ---------------------------------------------------------------------------
+# serving: a seeded trace of shot requests
+# ---------------------------------------------------------------------------
+def serving_trace(nreq=1000, rate=50.0, seed=4, sizes=None, steps=(1000, 4000)):
+    """Poisson arrivals (mean `rate` per second) of shot requests.
+
+    Each request: square grid n uniform over {256, 512, ..., 4096}; a layered
+    medium of 3-8 layers (sorted interface depths U(0, n), speeds
+    U[0.3, 0.57]) with 1-5 Gaussian blobs (+-10 %, sigma U[n/64, n/16]); a
+    Ricker source at (U[L, n-L), L) with fc = c_min / 20; 128 receivers on
+    row L; steps U{steps}; sponge L = min(64, n/8).
+    """
+    rng = np.random.default_rng(seed)
+    sizes = list(range(256, 4097, 256)) if sizes is None else list(sizes)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    for i in range(nreq):
+        n = int(sizes[int(rng.integers(0, len(sizes)))])
+        nl = int(rng.integers(3, 9))
+        depths = np.sort(rng.uniform(0, n, nl - 1))
+        speeds = rng.uniform(0.3, 0.57, nl)
+        nb = int(rng.integers(1, 6))
+        blobs = [(float(rng.uniform(0, n)), float(rng.uniform(0, n)),
+                  float(rng.uniform(n / 64.0, n / 16.0)), float(rng.uniform(-0.1, 0.1)))
+                 for _ in range(nb)]
+        L = min(64, n // 8)
+        sx = int(rng.integers(L, n - L))
+        nsteps = int(rng.integers(steps[0], steps[1] + 1))
+        reqs.append({"rid": i, "arrival": float(arrivals[i]), "n": n, "depths": depths,
+                     "speeds": speeds, "blobs": blobs, "sponge": L, "src": (sx, L),
+                     "nsteps": nsteps, "nrec": 128})
+    return reqs
+
+
+def serving_speed_numpy(req):
+    """Sound speed of a serving request (host, FP64): layer speed times
+    (1 + bump), bump = sum of blobs clipped to +-10 %."""
+    n = req["n"]
+    y = np.arange(n, dtype=np.float64)[:, None]
+    x = np.arange(n, dtype=np.float64)[None, :]
+    layer = np.searchsorted(req["depths"], np.arange(n), side="right")
+    cl = np.asarray(req["speeds"])[layer][:, None]
+    bump = np.zeros((n, n))
+    for bx, by, sg, a in req["blobs"]:
+        bump += a * np.exp(-((x - bx) ** 2 + (y - by) ** 2) / (2.0 * sg * sg))
+    return cl * (1.0 + np.clip(bump, -0.1, 0.1))
+
+
+def serving_speed_torch(req, device):
+    """The same medium built with torch on a device (for the serving loop,
+    where host-side generation would stall admission)."""
+    import torch
+    n = req["n"]
+    y = torch.arange(n, dtype=torch.float64, device=device)[:, None]
+    x = torch.arange(n, dtype=torch.float64, device=device)[None, :]
+    layer = np.searchsorted(req["depths"], np.arange(n), side="right")
+    cl = torch.as_tensor(np.asarray(req["speeds"])[layer], dtype=torch.float64, device=device)[:, None]
+    bump = torch.zeros((n, n), dtype=torch.float64, device=device)
+    for bx, by, sg, a in req["blobs"]:
+        bump += a * torch.exp(-((x - bx) ** 2 + (y - by) ** 2) / (2.0 * sg * sg))
+    return cl * (1.0 + torch.clamp(bump, -0.1, 0.1))
+
+
+def serving_receivers(req):
+    L = req["sponge"]
+    return surface_receivers(req["n"], req["nrec"], L, L)
+
+
+def serving_min_speed(req):
+    """Lower bound of the request's sound speed: slowest layer, blobs at -10 %."""
+    return float(np.min(req["speeds"])) * 0.9
+
+
+def serving_wavelet(req):
+    """Ricker wavelet at fc = c_min / 20 (>= 20 nodes per wavelength), from
+    the request's speed bound so that no device read is needed."""
+    return ricker_wavelet(req["nsteps"] + 1, serving_min_speed(req) / 20.0)

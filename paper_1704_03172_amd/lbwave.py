@@ -30,7 +30,10 @@ EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_workspace_bytes",
            "lb_set_source", "lb_record", "lb_record_sum_rho", "lb_step_n",
            "lb_get_time", "lb_get_field", "lb_get_field_fine",
            "lb_state_bytes", "lb_get_state", "lb_set_raw_state", "lb_sync",
-           "lb_status_string", "lb_device_copy")
+           "lb_status_string", "lb_device_copy",
+           "lb_batch_workspace_bytes", "lb_batch_create", "lb_shot_workspace_bytes",
+           "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times",
+           "lb_batch_sync", "lb_batch_destroy")
 
 
 class LBError(RuntimeError):
@@ -55,6 +58,16 @@ class Desc(ctypes.Structure):
         ("patch_overlap_out", ctypes.c_int32), ("patch_overlap_in", ctypes.c_int32),
         ("trace_capacity", ctypes.c_int64),
         ("max_receivers", ctypes.c_int32), ("_pad1", ctypes.c_int32),
+    ]
+
+
+class ShotDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("src_x", ctypes.c_int32), ("src_y", ctypes.c_int32),
+        ("nsteps", ctypes.c_int64),
+        ("sponge_width", ctypes.c_int32), ("nrec", ctypes.c_int32),
+        ("sponge_sigma_max", ctypes.c_double),
     ]
 
 
@@ -95,6 +108,18 @@ def lib():
         "lb_sync": (ctypes.c_int, [vp]),
         "lb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lb_device_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "lb_batch_workspace_bytes": (ctypes.c_size_t, [i32]),
+        "lb_batch_create": (ctypes.c_int, [PD, i32, vp, ctypes.c_size_t, vp, ctypes.c_int,
+                                           ctypes.POINTER(vp)]),
+        "lb_shot_workspace_bytes": (ctypes.c_size_t, [vp, ctypes.POINTER(ShotDesc)]),
+        "lb_batch_add_shot": (ctypes.c_int, [vp, ctypes.POINTER(ShotDesc), vp, ctypes.c_size_t, vp,
+                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                             i64, ctypes.POINTER(i32), vp, ctypes.POINTER(i32)]),
+        "lb_batch_remove_shot": (ctypes.c_int, [vp, i32]),
+        "lb_batch_tick": (ctypes.c_int, [vp, i64]),
+        "lb_batch_times": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+        "lb_batch_sync": (ctypes.c_int, [vp]),
+        "lb_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -303,3 +328,111 @@ def device_copy(dst, src, nbytes, stream=None):
     _check(lib().lb_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                                 ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(s.cuda_stream)),
            "lb_device_copy")
+
+
+def shot_desc(nx, ny, src, nsteps, nrec, sponge_width=0, sponge_sigma_max=0.0):
+    d = ShotDesc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.src_x, d.src_y = int(src[0]), int(src[1])
+    d.nsteps = int(nsteps)
+    d.nrec = int(nrec)
+    d.sponge_width = int(sponge_width)
+    d.sponge_sigma_max = float(sponge_sigma_max)
+    return d
+
+
+class Batch:
+    """Batched executor: many shots advance together in one launch per step,
+    captured as a HIP graph per tick (lb_batch_* calls).
+
+    Runs on its own (default-priority) stream so that ticks can be captured.
+    """
+
+    def __init__(self, max_shots, lattice=5, collision="bgk", precision="f32", tau=0.5,
+                 s=None, ratio=0.25, use_graph=True, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.scheme = make_desc(1, 1, lattice=lattice, collision=collision, precision=precision,
+                                tau=tau, s=s, ratio=ratio)
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.max_shots = int(max_shots)
+        self.stream = torch.cuda.Stream(self.device)
+        L = lib()
+        nbytes = L.lb_batch_workspace_bytes(self.max_shots)
+        if nbytes == 0:
+            raise LBError(-2, "lb_batch_workspace_bytes")
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(L.lb_batch_create(ctypes.byref(self.scheme), self.max_shots,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(int(nbytes)),
+                                 ctypes.c_void_p(self.stream.cuda_stream), 1 if use_graph else 0,
+                                 ctypes.byref(h)), "lb_batch_create")
+        self._h = h
+        self.shots = {}
+
+    def shot_bytes(self, desc):
+        return int(lib().lb_shot_workspace_bytes(self._h, ctypes.byref(desc)))
+
+    def add(self, desc, c2, wavelet, receivers):
+        """Admit a shot; returns its slot.  c2: numpy array or CUDA tensor."""
+        torch = self._torch
+        nbytes = self.shot_bytes(desc)
+        if nbytes == 0:
+            raise LBError(-2, "lb_shot_workspace_bytes")
+        rec = np.ascontiguousarray(receivers, dtype=np.int32).reshape(-1, 2)
+        if rec.shape[0] != desc.nrec:
+            raise ValueError("receiver count does not match the shot description")
+        w = np.ascontiguousarray(wavelet, dtype=np.float64)
+        keep = []
+        if isinstance(c2, torch.Tensor) and c2.is_cuda:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            c2 = c2.contiguous()
+            keep.append(c2)
+            cp, ct, dev = ctypes.c_void_p(c2.data_ptr()), (F64 if c2.dtype == torch.float64 else F32), 1
+        else:
+            arr = np.ascontiguousarray(c2, dtype=np.float64)
+            keep.append(arr)
+            cp, ct, dev = ctypes.c_void_p(arr.ctypes.data), F64, 0
+        with torch.cuda.stream(self.stream):
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            traces = torch.zeros((max(desc.nrec, 1), desc.nsteps + 1), dtype=self.dtype, device=self.device)
+        slot = ctypes.c_int32(-1)
+        _check(lib().lb_batch_add_shot(self._h, ctypes.byref(desc), ctypes.c_void_p(ws.data_ptr()),
+                                       ctypes.c_size_t(nbytes), cp, ct, dev,
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(w.size),
+                                       rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       ctypes.c_void_p(traces.data_ptr()), ctypes.byref(slot)),
+               "lb_batch_add_shot")
+        self.shots[slot.value] = {"ws": ws, "traces": traces, "nsteps": int(desc.nsteps), "bytes": nbytes}
+        return slot.value
+
+    def remove(self, slot):
+        """Retire a shot; returns its trace tensor [nrec][nsteps + 1]."""
+        _check(lib().lb_batch_remove_shot(self._h, int(slot)), "lb_batch_remove_shot")
+        info = self.shots.pop(int(slot))
+        return info["traces"]
+
+    def tick(self, k):
+        _check(lib().lb_batch_tick(self._h, int(k)), "lb_batch_tick")
+
+    def times(self):
+        out = (ctypes.c_int64 * self.max_shots)()
+        _check(lib().lb_batch_times(self._h, out), "lb_batch_times")
+        return np.frombuffer(out, dtype=np.int64).copy()
+
+    def sync(self):
+        _check(lib().lb_batch_sync(self._h), "lb_batch_sync")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            code = lib().lb_batch_destroy(self._h)
+            self._h = None
+            _check(code, "lb_batch_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
