@@ -55,7 +55,7 @@ class ShotServer:
 
     def __init__(self, budget_bytes=64 << 30, max_slots=32, tick_steps=None,
                  precision="f32", use_graph=True, keep_traces=False, batch=None,
-                 policy="fifo", node_cap=2 * 4096 * 4096, tick_ms=20.0, rate_lups=1.3e11):
+                 policy="sjf", node_cap=4096 * 4096, tick_ms=20.0, rate_lups=1.3e11):
         import torch
         from . import lbwave
         self.torch = torch
@@ -188,8 +188,8 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--tick", type=int, default=None, help="fixed steps per tick (default: adaptive)")
-    ap.add_argument("--policy", choices=("fifo", "sjf"), default="fifo")
-    ap.add_argument("--node-cap", type=int, default=2 * 4096 * 4096)
+    ap.add_argument("--policy", choices=("fifo", "sjf"), default="sjf")
+    ap.add_argument("--node-cap", type=int, default=4096 * 4096)
     ap.add_argument("--mode", choices=("batch", "fifo", "both"), default="both")
     args = ap.parse_args(argv)
     import torch

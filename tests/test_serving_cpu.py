@@ -96,7 +96,8 @@ def test_server_admission_and_completion():
         pytest.skip("library not built")
     trace = inputs.serving_trace(12, 1e6, seed=4, sizes=[256, 512], steps=(100, 400))
     fb = FakeBatch(3)
-    srv = serve.ShotServer(budget_bytes=44 * 512 * 512 * 2 + 10000, max_slots=3, tick_steps=50, batch=fb)
+    srv = serve.ShotServer(budget_bytes=44 * 512 * 512 * 2 + 10000, max_slots=3, tick_steps=50, batch=fb,
+                           policy="fifo")
     recs, summary = srv.run(trace)
     assert summary["completed"] == 12
     assert fb.peak <= 3
