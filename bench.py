@@ -82,6 +82,82 @@ def copy_bandwidth(torch, lbwave, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / t / 1e9
 
 
+def refined_variant(torch, lbwave, inputs, coarse_steps=300):
+    """Refinement: 2048^2 coarse D2Q5 MRT FP32 with the 1024 x 512 fine patch
+    over a low-velocity lens; MLUPS counts coarse and fine lattice updates."""
+    rw = inputs.refined_workload(n=2048, nsteps=coarse_steps + 100)
+    g = lbwave.Grid(2048, 2048, lattice=5, collision="mrt", precision="f32",
+                    s=[1, 1, 1, 2, 2], sponge_width=rw["sponge_width"],
+                    sponge_sigma_max=rw["sponge_sigma_max"], patch=rw["patch"],
+                    trace_capacity=coarse_steps + 12, max_receivers=len(rw["receivers"]))
+    g.set_medium(rw["c2"])
+    g.set_medium(rw["c2_fine"], fine=True)
+    g.set_source(rw["source"][0], rw["source"][1], rw["wavelet"])
+    g.record(rw["receivers"])
+    tv = time_steps(torch, g, coarse_steps, 10)
+    nf = g.fine_shape[0] * g.fine_shape[1]
+    lups = 2048 * 2048 * coarse_steps + 2 * nf * coarse_steps
+    log("refined %.0f MLUPS" % (lups / tv / 1e6))
+    g.close()
+    return {"refined_D2Q5_MRT_F32_2048": {
+        "MLUPS": round(lups / tv / 1e6, 1), "coarse_steps": coarse_steps,
+        "fine_nodes": nf, "ms_per_coarse_step": round(tv / coarse_steps * 1e3, 4)}}
+
+
+def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
+    """Gradient of the summed trace misfit of `nshots` shots w.r.t. c^2:
+    per shot a checkpointed forward run (FP32) and lb_adjoint; FP64
+    gradient sum.  Observed data come from forward runs in the true medium
+    (not timed)."""
+    wl = inputs.adjoint_workload(n=n, nshots=nshots, nsteps=nsteps)
+    rec = wl["receivers"]
+    g = lbwave.Grid(n, n, precision="f32", sponge_width=wl["sponge_width"],
+                    sponge_sigma_max=wl["sponge_sigma_max"], trace_capacity=nsteps + 1,
+                    max_receivers=len(rec), ckpt_every=K, ckpt_capacity=nsteps // K + 1)
+    obs = []
+    g.set_medium(wl["c2_true"])
+    for src in wl["sources"]:
+        g.set_state(np.zeros((n, n)))
+        g.set_source(src[0], src[1], wl["wavelet"])
+        tr = g.record(rec, fields=("p",))
+        g.step(nsteps)
+        obs.append(tr[0].clone())
+    g.set_medium(wl["c2_init"])
+    grad = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    phi = torch.zeros((), dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_fwd = t_adj = 0.0
+    g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, src in enumerate(wl["sources"]):
+        g.set_state(np.zeros((n, n)))
+        g.set_source(src[0], src[1], wl["wavelet"])
+        g.record(rec, fields=("p",))
+        ev[0].record(g.stream)
+        g.step(nsteps)
+        ev[1].record(g.stream)
+        p, res = g.misfit(obs[k], nsteps)
+        grad += g.adjoint(res, nsteps)
+        phi += p
+        ev[2].record(g.stream)
+        ev[2].synchronize()
+        t_fwd += ev[0].elapsed_time(ev[1]) / 1e3
+        t_adj += ev[1].elapsed_time(ev[2]) / 1e3
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    finite = bool(torch.isfinite(grad).all().item())
+    g.close()
+    N = n * n
+    return {"workload": "%d shots, %dx%d, %d steps, checkpoints every %d, FP32 state, FP64 gradient"
+                        % (nshots, n, n, nsteps, K),
+            "seconds_total": round(wall, 3), "ms_per_shot": round(wall / nshots * 1e3, 2),
+            "forward_ms_per_shot": round(t_fwd / nshots * 1e3, 2),
+            "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
+            "adjoint_phase_GB_s": round((44 + 64) * N * nsteps / (t_adj / nshots) / 1e9, 1),
+            "misfit": float(phi.item()), "gradient_finite": finite}
+
+
 def measured_traffic():
     """HBM bytes per step launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or None when
@@ -133,6 +209,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--refined-only", action="store_true",
+                    help="time only the refinement workload (for profiling)")
+    ap.add_argument("--adj-n", type=int, default=2048)
+    ap.add_argument("--adj-shots", type=int, default=16)
+    ap.add_argument("--adj-steps", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -145,6 +227,10 @@ def main():
     from paper_1704_03172_amd import inputs, lbwave
     torch.cuda.set_device(0)
     lbwave.lib()
+
+    if args.refined_only:
+        print(json.dumps(refined_variant(torch, lbwave, inputs)), flush=True)
+        return
 
     steps, warmup = args.steps, args.warmup
     log("building layered workload %d^2" % args.n)
@@ -185,25 +271,11 @@ def main():
             g.close()
             del g
             torch.cuda.empty_cache()
-        # refinement: 2048^2 coarse D2Q5 MRT with the 1024 x 512 fine patch
-        rw = inputs.refined_workload(n=2048, nsteps=400)
-        g = lbwave.Grid(2048, 2048, lattice=5, collision="mrt", precision="f32",
-                        s=[1, 1, 1, 2, 2], sponge_width=rw["sponge_width"],
-                        sponge_sigma_max=rw["sponge_sigma_max"], patch=rw["patch"],
-                        trace_capacity=402, max_receivers=len(rw["receivers"]))
-        g.set_medium(rw["c2"])
-        g.set_medium(rw["c2_fine"], fine=True)
-        g.set_source(rw["source"][0], rw["source"][1], rw["wavelet"])
-        g.record(rw["receivers"])
-        tv = time_steps(torch, g, 300, 10)
-        nf = g.fine_shape[0] * g.fine_shape[1]
-        lups = 2048 * 2048 * 300 + 2 * nf * 300
-        variants["refined_D2Q5_MRT_F32_2048"] = {
-            "MLUPS": round(lups / tv / 1e6, 1), "coarse_steps": 300,
-            "fine_nodes": nf, "ms_per_coarse_step": round(tv / 300 * 1e3, 4)}
-        log("refined %.0f MLUPS" % (lups / tv / 1e6))
-        g.close()
-        del g
+        variants.update(refined_variant(torch, lbwave, inputs))
+
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_bench(torch, lbwave, inputs, args.adj_n, args.adj_shots, args.adj_steps)
 
     serving = None
     if not args.no_serving:
@@ -248,6 +320,7 @@ def main():
         "traces_finite": finite,
         "variants": variants,
         "serving": serving,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -102,6 +102,11 @@ typedef struct lb_grid lb_grid;
  *                  the patch receives the fine solution.
  *   trace_capacity number of time columns of the trace / sum-rho arrays.
  *   max_receivers  receivers that lb_record may register.
+ *   ckpt_every     K > 0 enables lb_adjoint: lb_step_n keeps a checkpoint of
+ *                  the state at every time that is a multiple of K (and the
+ *                  workspace grows by ckpt_capacity states, K rho fields and
+ *                  two adjoint population sets).  0: no checkpoints.
+ *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
  *   nbatch         independent shots sharing the grid shape (must be 1).
  */
 typedef struct {
@@ -122,6 +127,8 @@ typedef struct {
     int32_t patch_overlap_out, patch_overlap_in;
     int64_t trace_capacity;
     int32_t max_receivers;
+    int32_t ckpt_every;
+    int32_t ckpt_capacity;
     int32_t _pad1;
 } lb_grid_desc;
 
@@ -212,6 +219,27 @@ int lb_get_field_fine(lb_grid *h, uint32_t what, void *d_out);
 size_t lb_state_bytes(const lb_grid *h);
 int lb_get_state(lb_grid *h, void *d_out);
 int lb_set_raw_state(lb_grid *h, const void *d_in);
+
+/* Misfit of the recorded pressure traces against observed data:
+ * res = p - d_obs and phi = 1/2 sum_r sum_{n <= nt} res^2 (FP64, fixed
+ * summation order).  d_obs and d_res are device arrays [nrec][trace_capacity]
+ * of the arithmetic type (columns 0..nt used); d_phi one device double.
+ * Needs receivers recorded with LB_FIELD_P. */
+int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res,
+              double *d_phi);
+
+/* Gradient of a trace misfit with respect to the per-node c^2 by the
+ * discrete adjoint of the scheme (the paper's update differentiated exactly:
+ * transpose of streaming and collision, source, sponge and receiver terms,
+ * and the dependence of the initial equilibrium on the weights).
+ * d_res [nrec][trace_capacity] holds dL/dp_r(n) for n = 0..nt (for the L2
+ * misfit, the residual of lb_misfit); d_grad receives dL/dc^2 [ny][nx] in
+ * FP64.  Needs ckpt_every > 0, receivers recorded, no patch, and a forward
+ * run of exactly nt steps from lb_set_state (or the rest state) with the
+ * same medium and source.  The forward segments are recomputed from the
+ * checkpoints; afterwards the population state is no longer the forward
+ * state, so stepping again needs lb_set_state or lb_set_raw_state first. */
+int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad);
 
 /* Wait for all work enqueued by the handle; returns the sticky error. */
 int lb_sync(lb_grid *h);

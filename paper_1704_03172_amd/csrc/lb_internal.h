@@ -35,23 +35,6 @@ struct Collision {
     double ratio = 0.0;                // D2Q9 w5 / w1
 };
 
-// One launch of the fused step (or of the collide-only variant).
-struct StepParams {
-    const void *src = nullptr;         // populations read
-    void *dst = nullptr;               // populations written
-    const void *c2 = nullptr;          // c^2 per node, compute type
-    int32_t nx = 0, ny = 0;
-    int64_t pstride = 0;               // elements between populations
-    int32_t q = 5;
-    Collision coll;
-    int32_t sponge_width = 0;
-    double sponge_smax = 0.0;
-    int32_t src_x = -1, src_y = -1;    // source node
-    double s_n = 0.0;                  // source amplitude of this time
-    Receivers rec;
-    double *partial = nullptr;         // per-block sums of rho (nullptr: off)
-};
-
 // Interface geometry of a factor-2 refinement patch (coarse units).
 struct PatchGeom {
     int32_t X0 = 0, Y0 = 0;            // fine node (0, 0) at coarse (X0, Y0)
@@ -76,7 +59,7 @@ struct InterfaceParams {
     PatchGeom g;
     GridRef coarse;                    // coarse state read
     GridRef fine;                      // fine state read (restriction)
-    void *snap = nullptr;              // [5][nsnap] ring-line snapshot
+    void *snap = nullptr;              // [5][nsnap] ring-line snapshot of time T
     double a_snap = 0.0, a_now = 1.0;  // prolongation: a_snap*snap + a_now*coarse
     void *dst = nullptr;               // populations written (fine or coarse)
     const void *dst_c2 = nullptr;      // c^2 of the written grid
@@ -88,6 +71,57 @@ struct InterfaceParams {
     double sponge_smax = 0.0;
     uint32_t field = 0;                // nonzero: write this LB_FIELD_* of the
     void *field_out = nullptr;         // interface state instead of populations
+    void *ring_out = nullptr;          // prolongation pair: [2][5][nring] post-collision
+                                       // ring states of fine times T+1 (mid), T+2 (end)
+};
+
+// One launch of the fused step (or of the collide-only variant).
+struct StepParams {
+    const void *src = nullptr;         // populations read
+    void *dst = nullptr;               // populations written
+    const void *c2 = nullptr;          // c^2 per node, compute type
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;               // elements between populations
+    int32_t q = 5;
+    Collision coll;
+    int32_t sponge_width = 0;
+    double sponge_smax = 0.0;
+    int32_t src_x = -1, src_y = -1;    // source node
+    double s_n = 0.0;                  // source amplitude of this time
+    Receivers rec;
+    double *partial = nullptr;         // per-block sums of rho (nullptr: off)
+    void *rho_out = nullptr;           // [ny][nx] pre-collision rho (nullptr: off)
+    void *snap = nullptr;              // refinement ring-line snapshot [5][snap_n]
+    int32_t snap_x0 = 0, snap_y0 = 0;  // ring line: rows Y0, Y0+H over x in
+    int32_t snap_w = 0, snap_h = 0;    // [X0-1, X0+W+1]; columns X0, X0+W over
+    int32_t snap_n = 0;                // y in [Y0-1, Y0+H+1]
+    const void *ring_buf = nullptr;    // fine grid of a patch: post-collision outer-ring
+    int32_t ring_n = 0;                // states [5][ring_n] taken from the coarse grid
+    int32_t restrict_on = 0;           // fine grid of a patch: also write the coarse
+    InterfaceParams iface;             // inner ring from this launch's pre-collision
+};                                     // state (iface: as for launch_restrict)
+
+// One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
+// lambda(n) = K^T (1 - sigma) P^T lambda(n+1) + r(n), with the gradient
+// terms of time n accumulated into grad (FP64).
+struct AdjointParams {
+    const void *lam_next = nullptr;    // lambda(n+1) [q][pstride], compute type
+    void *lam = nullptr;               // lambda(n) written
+    const void *rho = nullptr;         // forward pre-collision rho(n) [ny][nx]
+    const void *c2 = nullptr;
+    double *grad = nullptr;            // [ny][nx]
+    int32_t nx = 0, ny = 0;
+    int64_t pstride = 0;
+    int32_t q = 5;
+    Collision coll;
+    double dw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // d w_i / d c^2
+    int32_t sponge_width = 0;
+    double sponge_smax = 0.0;
+    int32_t src_x = -1, src_y = -1;
+    double s_n = 0.0;                  // S(n)
+    Receivers rec;                     // tables + residual array in `traces`
+    int32_t terminal = 0;              // 1: n = N (no step, lambda(N+1) = 0)
+    int32_t initial = 0;               // 1: n = 0, add the initial-state term
 };
 
 // Field extraction: one field of the state at the current time.
@@ -136,6 +170,9 @@ struct BatchParams {
 };
 
 // Launchers (lb_kernels.hip).  All return the launch status.
+hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s);
+hipError_t launch_misfit(int storage, const void *traces, const void *obs, void *res, int32_t nrec,
+                         int64_t cap, int64_t ncols, double *phi, hipStream_t s);
 int step_vwidth(int storage);
 int step_tile_nodes(int storage);   // x-nodes covered by one step block
 hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s);
@@ -155,12 +192,13 @@ hipError_t launch_convert_c2(int storage, const void *in, int in_f64,
                              int32_t *bad_count, hipStream_t s);
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
 hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s);
-hipError_t launch_snapshot(int storage, const InterfaceParams &p,
-                           hipStream_t s);
 hipError_t launch_prolong(int storage, const InterfaceParams &p,
                           hipStream_t s);
 hipError_t launch_restrict(int storage, const InterfaceParams &p,
                            hipStream_t s);
+// The fine outer-ring states of one coarse step (p.ring_out), see
+// InterfaceParams::ring_out.
+hipError_t launch_prolong_pair(int storage, const InterfaceParams &p, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes,
                        hipStream_t s);
 

@@ -206,6 +206,147 @@ __device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, 
     if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
 }
 
+// ---- refinement interface (D2Q5, factor 2) -------------------------------------
+template <typename S, typename T>
+__device__ inline void pre_at(const GridRef &r, int x, int y, T (&g)[5]) {
+    const S *pop = reinterpret_cast<const S *>(r.pop);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        int xs = r.pre ? x : wrapi(x - cxv<5>(i), r.nx);
+        int ys = r.pre ? y : wrapi(y - cyv<5>(i), r.ny);
+        g[i] = T(pop[i * r.pstride + (int64_t)ys * r.nx + xs]);
+    }
+}
+
+// Snapshot layout (written by the coarse step, see update_tile): top row
+// (y = Y0, x = X0-1 .. X0+W+1), bottom row (y = Y0+H), left column (x = X0,
+// y = Y0-1 .. Y0+H+1), right column (x = X0+W).
+
+// R_f(g) = g^eq(rho(g), J(g)) + f (g - g^eq) with the weights of the
+// receiving node's c^2 (eq. coarse-fine dist connect), then the collision
+// (and sponge) of the receiving grid; written as the post-collision state at
+// node (x, y) of dst.
+template <typename S, int KIND>
+__device__ inline void rescale_collide(const InterfaceParams &p, typename Tr<S>::T (&gh)[5], int x, int y,
+                                       typename Tr<S>::T (&out)[5]) {
+    using T = typename Tr<S>::T;
+    const int64_t k = (int64_t)y * p.dst_nx + x;
+    const T c2 = reinterpret_cast<const T *>(p.dst_c2)[k];
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        rho += gh[i];
+        jx += T(cxv<5>(i)) * gh[i];
+        jy += T(cyv<5>(i)) * gh[i];
+    }
+    T w[5];
+    weights<T, 5>(c2, p.coll, w);
+    T gr[5];
+    const T f = T(p.f);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        T geq = w[i] * rho + (i == 0 ? T(0) : T(0.5) * (T(cxv<5>(i)) * jx + T(cyv<5>(i)) * jy));
+        gr[i] = geq + f * (gh[i] - geq);
+    }
+    collide<T, 5, KIND>(gr, c2, p.coll, out, w);
+    const T sf = sponge_factor<T>(x, y, p.dst_nx, p.dst_ny, p.sponge_width, p.sponge_smax);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) out[i] *= sf;
+}
+
+template <typename S, int KIND>
+__device__ inline void rescale_collide_store_impl(const InterfaceParams &p, typename Tr<S>::T (&gh)[5], int x, int y) {
+    using T = typename Tr<S>::T;
+    const int64_t k = (int64_t)y * p.dst_nx + x;
+    if (p.field) {   // R_f keeps rho and J: the node's fields are those of gh
+        T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            rho += gh[i];
+            jx += T(cxv<5>(i)) * gh[i];
+            jy += T(cyv<5>(i)) * gh[i];
+        }
+        const T c2 = reinterpret_cast<const T *>(p.dst_c2)[k];
+        T v = p.field == 1u ? c2 * rho : p.field == 2u ? rho : p.field == 4u ? jx : jy;
+        reinterpret_cast<T *>(p.field_out)[k] = v;
+        return;
+    }
+    T out[5];
+    rescale_collide<S, KIND>(p, gh, x, y, out);
+    S *dst = reinterpret_cast<S *>(p.dst);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dst[i * p.dst_pstride + k] = S(out[i]);
+}
+
+// Interpolation stencil of fine outer-ring node (i, j): coincident nodes
+// copy the coarse node (weight 1 on entry 1, the other entries repeat it with
+// weight 0), mid-edge nodes take the cubic (-1, 9, 9, -1)/16 along their
+// edge.  nodes_*: coarse nodes; sidx: their ring-line snapshot entries.
+template <typename T>
+__device__ inline void ring_stencil(const PatchGeom &g, int i, int j, int (&nodes_x)[4], int (&nodes_y)[4],
+                                    int (&sidx)[4], T (&wt)[4]) {
+    const int nh = g.W + 3, nv = g.H + 3;
+    const bool horiz = (j == 0 || j == g.nyf - 1);
+    const int hbase = (j == 0) ? 0 : nh;                 // top / bottom arrays
+    const int vbase = 2 * nh + ((i == 0) ? 0 : nv);      // left / right arrays
+    if ((i & 1) == 0 && (j & 1) == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = g.X0 + i / 2;
+            nodes_y[s] = g.Y0 + j / 2;
+            wt[s] = s == 1 ? T(1) : T(0);
+            sidx[s] = horiz ? hbase + i / 2 + 1 : vbase + j / 2 + 1;
+        }
+    } else if (i & 1) {
+        const int a = g.X0 + (i - 1) / 2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = a - 1 + s;
+            nodes_y[s] = g.Y0 + j / 2;
+            sidx[s] = hbase + (i - 1) / 2 + s;
+        }
+        wt[0] = wt[3] = T(-1) / T(16);
+        wt[1] = wt[2] = T(9) / T(16);
+    } else {
+        const int b = g.Y0 + (j - 1) / 2;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nodes_x[s] = g.X0 + i / 2;
+            nodes_y[s] = b - 1 + s;
+            sidx[s] = vbase + (j - 1) / 2 + s;
+        }
+        wt[0] = wt[3] = T(-1) / T(16);
+        wt[1] = wt[2] = T(9) / T(16);
+    }
+}
+
+// Coarse state interpolated to fine outer-ring node (i, j) along the edge;
+// in time a_snap * (snapshot of T) + a_now * (coarse now).
+template <typename S>
+__device__ inline void ring_interp(const InterfaceParams &p, int i, int j, typename Tr<S>::T (&gh)[5]) {
+    using T = typename Tr<S>::T;
+    const PatchGeom &g = p.g;
+    int nodes_x[4], nodes_y[4], sidx[4];
+    T wt[4];
+    ring_stencil<T>(g, i, j, nodes_x, nodes_y, sidx, wt);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) gh[q] = T(0);
+    const T *snap = reinterpret_cast<const T *>(p.snap);
+    const T an = T(p.a_now), as = T(p.a_snap);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (wt[s] == T(0)) continue;
+        T gn[5];
+        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            T v = an * gn[q];
+            if (p.a_snap != 0.0) v += as * snap[q * g.nsnap + sidx[s]];
+            gh[q] += wt[s] * v;
+        }
+    }
+}
+
 // ---- fused step -------------------------------------------------------------
 // One thread's share of the update: V consecutive nodes (x0 .. x0+V-1) of row
 // y.  Returns the FP64 sum of rho over them when p.partial is set.
@@ -242,6 +383,29 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
         }
     }
 
+    // refinement: the pre-collision state of this time on the coarse ring
+    // line feeds the temporal interpolation of the next coarse step
+    if (Q == 5 && p.snap) {
+        T *snap = reinterpret_cast<T *>(p.snap);
+        const int X0 = p.snap_x0, Y0 = p.snap_y0, W = p.snap_w, H = p.snap_h;
+        const int nh = W + 3, nv = H + 3;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int x = x0 + j;
+            if (x >= nx) break;
+            if ((y == Y0 || y == Y0 + H) && x >= X0 - 1 && x <= X0 + W + 1) {
+                const int t = (y == Y0 ? 0 : nh) + (x - (X0 - 1));
+#pragma unroll
+                for (int i = 0; i < Q; ++i) snap[i * p.snap_n + t] = g[i][j];
+            }
+            if ((x == X0 || x == X0 + W) && y >= Y0 - 1 && y <= Y0 + H + 1) {
+                const int t = 2 * nh + (x == X0 ? 0 : nv) + (y - (Y0 - 1));
+#pragma unroll
+                for (int i = 0; i < Q; ++i) snap[i * p.snap_n + t] = g[i][j];
+            }
+        }
+    }
+
     // receivers of this row (CSR lookup; rows without receivers cost one
     // uniform pair of loads)
     int rb = 0, re = 0;
@@ -273,11 +437,12 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
             for (; lo < re && p.rec.xs[lo] == x; ++lo)
                 write_fields<T>(p.rec, p.rec.slot[lo], rho, jx, jy, c2v[j]);
         }
-        if (p.partial && x < nx) {
+        if ((p.partial || p.rho_out) && x < nx) {
             T rho = T(0);
 #pragma unroll
             for (int i = 0; i < Q; ++i) rho += gj[i];
             local += double(rho);
+            if (p.rho_out) reinterpret_cast<T *>(p.rho_out)[(int64_t)y * nx + x] = rho;
         }
         collide<T, Q, KIND>(gj, c2v[j], p.coll, gs, w);
         if (y == p.src_y && x == p.src_x) {
@@ -288,6 +453,26 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
         const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
 #pragma unroll
         for (int i = 0; i < Q; ++i) outv[i][j] = S(gs[i] * sf);
+        if constexpr (Q == 5) {
+            if (p.restrict_on && x < nx && !((x | y) & 1)) {
+                // this fine node coincides with a coarse node: on the coarse
+                // inner ring, its state (R_2, then the coarse collision)
+                // replaces the coarse grid's own
+                const PatchGeom &pg = p.iface.g;
+                const int X = pg.X0 + (x >> 1), Y = pg.Y0 + (y >> 1);
+                if (X >= pg.xa && X <= pg.xb && Y >= pg.ya && Y <= pg.yb &&
+                    (X == pg.xa || X == pg.xb || Y == pg.ya || Y == pg.yb))
+                    rescale_collide_store_impl<S, KIND>(p.iface, gj, X, Y);
+            }
+            if (p.ring_buf && x < nx && (y == 0 || y == ny - 1 || x == 0 || x == nx - 1)) {
+                // outer ring of a fine grid: the state comes from the coarse
+                // grid, not from streaming
+                const int r = y == 0 ? x : y == ny - 1 ? nx + x : x == 0 ? 2 * nx + y - 1 : 2 * nx + ny - 2 + y - 1;
+                const T *rb = reinterpret_cast<const T *>(p.ring_buf);
+#pragma unroll
+                for (int i = 0; i < 5; ++i) outv[i][j] = S(rb[i * p.ring_n + r]);
+            }
+        }
     }
     S *dst = reinterpret_cast<S *>(p.dst);
 #pragma unroll
@@ -315,6 +500,168 @@ __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
             p.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
         }
     }
+}
+
+// ---- discrete adjoint (gradient of the trace misfit w.r.t. c^2) -----------------
+// Backward step n: mu(x) = (1 - sigma(x)) lambda(n+1)(x + c_i) (transpose of
+// the pull), nu = C mu (C symmetric; its conserved rows drop out of every
+// term below), lambda(n) = mu - nu + E^T nu with
+// (E^T nu)_j = sum_i w_i nu_i + c_j . sum_i (w_i / c^2) c_i nu_i, plus the
+// receiver residuals c^2(x_r) r_r(n) on every population.  Gradient terms of
+// time n: rho(n) dw . nu, S(n) dw . mu at the source node, r_r(n) rho(n) at
+// receivers, and at n = 0 rho(0) dw . lambda(0) (g(0) is an equilibrium).
+// lambda is single-use per step, so it streams like the forward populations.
+template <typename T, int Q, int KIND>
+__global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
+    constexpr int V = Tr<T>::V;
+    const int y = blockIdx.y;
+    const int x0 = (blockIdx.x * kStepBlock + threadIdx.x) * V;
+    const int nx = p.nx, ny = p.ny;
+    if (x0 >= nx) return;
+    T mu[Q][V];
+    if (p.terminal) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int j = 0; j < V; ++j) mu[i][j] = T(0);
+    } else {
+        const T *ln = reinterpret_cast<const T *>(p.lam_next);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ys = wrapi(y + cyv<Q>(i), ny);
+            T t[V];
+            load_x<T, V>(ln + i * p.pstride + (int64_t)ys * nx, x0 + cxv<Q>(i), nx, t);
+#pragma unroll
+            for (int j = 0; j < V; ++j) mu[i][j] = t[j];
+        }
+    }
+    T c2v[V], rhov[V];
+    {
+        const T *c2row = reinterpret_cast<const T *>(p.c2) + (int64_t)y * nx;
+        const T *rrow = reinterpret_cast<const T *>(p.rho) + (int64_t)y * nx;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int x = min(x0 + j, nx - 1);
+            c2v[j] = c2row[x];
+            rhov[j] = rrow[x];
+        }
+    }
+    int rb = 0, re = 0;
+    if (p.rec.row_ptr) {
+        rb = p.rec.row_ptr[y];
+        re = p.rec.row_ptr[y + 1];
+    }
+    const T *res = reinterpret_cast<const T *>(p.rec.traces);
+    T outv[Q][V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
+        T m[Q], nu[Q], w[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) m[i] = mu[i][j] * sf;
+        if (KIND == 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) nu[i] = T(p.coll.omega) * m[i];
+        } else {
+            T r[9];
+#pragma unroll
+            for (int k = 3; k < Q; ++k) {
+                T a = T(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const int c = mrow<Q>(k, i);
+                    if (c != 0) a += T(c) * m[i];
+                }
+                r[k] = T(p.coll.srate[k]) * a;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                T a = T(0);
+#pragma unroll
+                for (int k = 3; k < Q; ++k) {
+                    const int c = mrow<Q>(k, i);
+                    if (c != 0) a += T(c) * r[k];
+                }
+                nu[i] = a;
+            }
+        }
+        double gacc = 0.0;
+        {
+            double dn = 0.0, dm = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                dn += p.dw[i] * double(nu[i]);
+                dm += p.dw[i] * double(m[i]);
+            }
+            gacc += double(rhov[j]) * dn;
+            if (y == p.src_y && x == p.src_x) gacc += p.s_n * dm;
+        }
+        weights<T, Q>(c2v[j], p.coll, w);
+        T s0 = T(0), sxv = T(0), syv = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            s0 += w[i] * nu[i];
+            const T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(p.coll.kax) : T(p.coll.kdg));
+            if (i > 0) {
+                sxv += kj * T(cxv<Q>(i)) * nu[i];
+                syv += kj * T(cyv<Q>(i)) * nu[i];
+            }
+        }
+        T lam[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            lam[i] = m[i] - nu[i] + s0 + T(cxv<Q>(i)) * sxv + T(cyv<Q>(i)) * syv;
+        if (rb < re && x < nx) {
+            int lo = rb, hi = re;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
+            }
+            for (; lo < re && p.rec.xs[lo] == x; ++lo) {
+                const T rr = res[(int64_t)p.rec.slot[lo] * p.rec.cap + p.rec.col];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lam[i] += c2v[j] * rr;
+                gacc += double(rr) * double(rhov[j]);
+            }
+        }
+        if (p.initial) {
+            double dl = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dl += p.dw[i] * double(lam[i]);
+            gacc += double(rhov[j]) * dl;
+        }
+        if (x < nx) p.grad[(int64_t)y * nx + x] += gacc;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) outv[i][j] = lam[i];
+    }
+    T *lo = reinterpret_cast<T *>(p.lam);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) store_x<T, V>(lo + i * p.pstride + (int64_t)y * nx, x0, nx, outv[i]);
+}
+
+// Residual r = p - d and misfit phi = 1/2 sum r^2 over columns 0 .. ncols-1
+// of every receiver (one block, fixed summation order: deterministic).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_misfit(const T *traces, const T *obs, T *res, int32_t nrec, int64_t cap,
+                                                   int64_t ncols, double *phi) {
+    double s = 0.0;
+    const int64_t n = (int64_t)nrec * ncols;
+    for (int64_t k = threadIdx.x; k < n; k += kBlock) {
+        const int64_t r = k / ncols, c = k % ncols;
+        const int64_t idx = r * cap + c;
+        const T d = traces[idx] - obs[idx];
+        res[idx] = d;
+        s += double(d) * double(d);
+    }
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *phi = 0.5 * sh[0];
 }
 
 // ---- batched step over many shots (serving) ------------------------------------
@@ -457,79 +804,6 @@ __global__ __launch_bounds__(kBlock) void k_field(FieldParams p) {
     reinterpret_cast<T *>(p.out)[k] = v;
 }
 
-// ---- refinement interface (D2Q5, factor 2) -------------------------------------
-template <typename S, typename T>
-__device__ inline void pre_at(const GridRef &r, int x, int y, T (&g)[5]) {
-    const S *pop = reinterpret_cast<const S *>(r.pop);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        int xs = r.pre ? x : wrapi(x - cxv<5>(i), r.nx);
-        int ys = r.pre ? y : wrapi(y - cyv<5>(i), r.ny);
-        g[i] = T(pop[i * r.pstride + (int64_t)ys * r.nx + xs]);
-    }
-}
-
-// Snapshot layout: top row (y = Y0, x = X0-1 .. X0+W+1), bottom row
-// (y = Y0+H), left column (x = X0, y = Y0-1 .. Y0+H+1), right column (x = X0+W).
-__device__ inline void snap_node(const PatchGeom &g, int t, int &x, int &y) {
-    const int nh = g.W + 3, nv = g.H + 3;
-    if (t < nh) { x = g.X0 - 1 + t; y = g.Y0; }
-    else if (t < 2 * nh) { x = g.X0 - 1 + (t - nh); y = g.Y0 + g.H; }
-    else if (t < 2 * nh + nv) { x = g.X0; y = g.Y0 - 1 + (t - 2 * nh); }
-    else { x = g.X0 + g.W; y = g.Y0 - 1 + (t - 2 * nh - nv); }
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_snapshot(InterfaceParams p) {
-    using T = typename Tr<S>::T;
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= p.g.nsnap) return;
-    int x, y;
-    snap_node(p.g, t, x, y);
-    T g[5];
-    pre_at<S, T>(p.coarse, x, y, g);
-    T *snap = reinterpret_cast<T *>(p.snap);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) snap[i * p.g.nsnap + t] = g[i];
-}
-
-// R_f(g) = g^eq(rho(g), J(g)) + f (g - g^eq) with the weights of the
-// receiving node's c^2 (eq. coarse-fine dist connect), then the collision
-// (and sponge) of the receiving grid; written as the post-collision state at
-// node (x, y) of dst.
-template <typename S, int KIND>
-__device__ inline void rescale_collide_store_impl(const InterfaceParams &p, typename Tr<S>::T (&gh)[5], int x, int y) {
-    using T = typename Tr<S>::T;
-    const int64_t k = (int64_t)y * p.dst_nx + x;
-    const T c2 = reinterpret_cast<const T *>(p.dst_c2)[k];
-    T rho = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        rho += gh[i];
-        jx += T(cxv<5>(i)) * gh[i];
-        jy += T(cyv<5>(i)) * gh[i];
-    }
-    if (p.field) {   // R_f keeps rho and J: the node's fields are those of gh
-        T v = p.field == 1u ? c2 * rho : p.field == 2u ? rho : p.field == 4u ? jx : jy;
-        reinterpret_cast<T *>(p.field_out)[k] = v;
-        return;
-    }
-    T w[5];
-    weights<T, 5>(c2, p.coll, w);
-    T gr[5], gs[5];
-    const T f = T(p.f);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        T geq = w[i] * rho + (i == 0 ? T(0) : T(0.5) * (T(cxv<5>(i)) * jx + T(cyv<5>(i)) * jy));
-        gr[i] = geq + f * (gh[i] - geq);
-    }
-    collide<T, 5, KIND>(gr, c2, p.coll, gs, w);
-    const T sf = sponge_factor<T>(x, y, p.dst_nx, p.dst_ny, p.sponge_width, p.sponge_smax);
-    S *dst = reinterpret_cast<S *>(p.dst);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) dst[i * p.dst_pstride + k] = S(gs[i] * sf);
-}
-
 // Fine outer ring layout: top row (j = 0), bottom row (j = nyf-1), left
 // column (i = 0, j = 1 .. nyf-2), right column (i = nxf-1).
 template <typename S, int KIND>
@@ -543,58 +817,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(InterfaceParams p) {
     else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
     else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
     else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
-
-    // stencil: coarse nodes (cx_s, cy_s), snapshot indices, weights
-    int nodes_x[4], nodes_y[4], sidx[4];
-    T wt[4];
-    const int nh = g.W + 3, nv = g.H + 3;
-    const bool horiz = (j == 0 || j == g.nyf - 1);
-    const int hbase = (j == 0) ? 0 : nh;                 // top / bottom arrays
-    const int vbase = 2 * nh + ((i == 0) ? 0 : nv);      // left / right arrays
-    if ((i & 1) == 0 && (j & 1) == 0) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            nodes_x[s] = g.X0 + i / 2;
-            nodes_y[s] = g.Y0 + j / 2;
-            wt[s] = s == 1 ? T(1) : T(0);
-            sidx[s] = horiz ? hbase + i / 2 + 1 : vbase + j / 2 + 1;
-        }
-    } else if (i & 1) {
-        const int a = g.X0 + (i - 1) / 2;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            nodes_x[s] = a - 1 + s;
-            nodes_y[s] = g.Y0 + j / 2;
-            sidx[s] = hbase + (i - 1) / 2 + s;
-        }
-        wt[0] = wt[3] = T(-1) / T(16);
-        wt[1] = wt[2] = T(9) / T(16);
-    } else {
-        const int b = g.Y0 + (j - 1) / 2;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            nodes_x[s] = g.X0 + i / 2;
-            nodes_y[s] = b - 1 + s;
-            sidx[s] = vbase + (j - 1) / 2 + s;
-        }
-        wt[0] = wt[3] = T(-1) / T(16);
-        wt[1] = wt[2] = T(9) / T(16);
-    }
-    T gh[5] = {T(0), T(0), T(0), T(0), T(0)};
-    const T *snap = reinterpret_cast<const T *>(p.snap);
-    const T an = T(p.a_now), as = T(p.a_snap);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        if (wt[s] == T(0)) continue;
-        T gn[5];
-        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            T v = an * gn[q];
-            if (p.a_snap != 0.0) v += as * snap[q * g.nsnap + sidx[s]];
-            gh[q] += wt[s] * v;
-        }
-    }
+    T gh[5];
+    ring_interp<S>(p, i, j, gh);
     rescale_collide_store_impl<S, KIND>(p, gh, i, j);
 }
 
@@ -614,6 +838,57 @@ __global__ __launch_bounds__(kBlock) void k_restrict(InterfaceParams p) {
     T gf[5];
     pre_at<S, T>(p.fine, 2 * (x - g.X0), 2 * (y - g.Y0), gf);
     rescale_collide_store_impl<S, KIND>(p, gf, x, y);
+}
+
+// The outer-ring states of the two fine steps of one coarse step T -> T+2,
+// one thread per fine ring node: R_{1/2} of the coarse state interpolated to
+// the node, at T+1 (mean of the ring-line snapshot of T and the coarse state
+// of T+2) and at T+2, each followed by the fine collision.
+template <typename S, int KIND>
+__global__ __launch_bounds__(kBlock) void k_prolong_pair(InterfaceParams p) {
+    using T = typename Tr<S>::T;
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    const PatchGeom &g = p.g;
+    if (r >= g.nring) return;
+    int i, j;
+    if (r < g.nxf) { i = r; j = 0; }
+    else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
+    else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
+    else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
+    int nodes_x[4], nodes_y[4], sidx[4];
+    T wt[4];
+    ring_stencil<T>(g, i, j, nodes_x, nodes_y, sidx, wt);
+    // every load of the node up front (one round of memory latency); the
+    // weight-0 entries of a coincident node repeat a valid node
+    T gn[4][5], gs[4][5];
+    const T *snap = reinterpret_cast<const T *>(p.snap);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn[s]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gs[s][q] = snap[q * g.nsnap + sidx[s]];
+    }
+    T mid[5], end[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) mid[q] = end[q] = T(0);
+    const T half = T(0.5);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            mid[q] += wt[s] * (half * gn[s][q] + half * gs[s][q]);
+            end[q] += wt[s] * gn[s][q];
+        }
+    }
+    T *ro = reinterpret_cast<T *>(p.ring_out);
+    T out0[5], out1[5];
+    rescale_collide<S, KIND>(p, mid, i, j, out0);
+    rescale_collide<S, KIND>(p, end, i, j, out1);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        ro[k * g.nring + r] = out0[k];
+        ro[(5 + k) * g.nring + r] = out1[k];
+    }
 }
 
 // ---- dispatch helpers ----------------------------------------------------------
@@ -685,6 +960,33 @@ hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact
     return hipGetLastError();
 }
 
+hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s) {
+    const bool f64 = storage == ST_F64;
+    const int V = f64 ? Tr<double>::V : Tr<float>::V;
+    dim3 grid((unsigned)(((int64_t)p.nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)), (unsigned)p.ny);
+    const bool mrt = p.coll.kind == 1;
+#define LBW_A(TT, QQ)                                                                             \
+    do {                                                                                          \
+        if (mrt) hipLaunchKernelGGL((k_adjoint<TT, QQ, 1>), grid, dim3(kStepBlock), 0, s, p);     \
+        else hipLaunchKernelGGL((k_adjoint<TT, QQ, 0>), grid, dim3(kStepBlock), 0, s, p);         \
+    } while (0)
+    if (f64) { if (p.q == 5) LBW_A(double, 5); else LBW_A(double, 9); }
+    else { if (p.q == 5) LBW_A(float, 5); else LBW_A(float, 9); }
+#undef LBW_A
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit(int storage, const void *traces, const void *obs, void *res, int32_t nrec, int64_t cap,
+                         int64_t ncols, double *phi, hipStream_t s) {
+    if (storage == ST_F64)
+        hipLaunchKernelGGL(k_misfit<double>, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<const double *>(traces),
+                           reinterpret_cast<const double *>(obs), reinterpret_cast<double *>(res), nrec, cap, ncols, phi);
+    else
+        hipLaunchKernelGGL(k_misfit<float>, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<const float *>(traces),
+                           reinterpret_cast<const float *>(obs), reinterpret_cast<float *>(res), nrec, cap, ncols, phi);
+    return hipGetLastError();
+}
+
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
     return hipGetLastError();
@@ -743,14 +1045,6 @@ hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_snapshot(int storage, const InterfaceParams &p, hipStream_t s) {
-    dim3 grid(blocks_for(p.g.nsnap));
-    if (storage == ST_F32) hipLaunchKernelGGL(k_snapshot<float>, grid, dim3(kBlock), 0, s, p);
-    else if (storage == ST_F64) hipLaunchKernelGGL(k_snapshot<double>, grid, dim3(kBlock), 0, s, p);
-    else hipLaunchKernelGGL(k_snapshot<_Float16>, grid, dim3(kBlock), 0, s, p);
-    return hipGetLastError();
-}
-
 #define LBW_IFACE(KERNEL, N)                                                                       \
     dim3 grid(blocks_for(N));                                                                      \
     const bool mrt = p.coll.kind == 1;                                                             \
@@ -763,6 +1057,8 @@ hipError_t launch_snapshot(int storage, const InterfaceParams &p, hipStream_t s)
     return hipGetLastError();
 
 hipError_t launch_prolong(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong, p.g.nring) }
+
+hipError_t launch_prolong_pair(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong_pair, p.g.nring) }
 hipError_t launch_restrict(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_restrict, p.g.ninner) }
 
 }  // namespace lbw

@@ -62,6 +62,9 @@ int validate(const lb_grid_desc *d) {
     if (d->nbatch != 1) return LB_E_UNSUPPORTED;
     if (d->sponge_width < 0 || !(d->sponge_sigma_max >= 0.0 && d->sponge_sigma_max <= 1.0)) return LB_E_RANGE;
     if (d->trace_capacity < 0 || d->max_receivers < 0) return LB_E_RANGE;
+    if (d->ckpt_every < 0 || d->ckpt_capacity < 0) return LB_E_RANGE;
+    if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
+    if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -84,7 +87,8 @@ struct Layout {
     int64_t nblocks = 0;
     size_t pop[2] = {0, 0}, c2 = 0, rrow = 0, rxs = 0, rslot = 0;
     size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0;
-    size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, total = 0;
+    size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, ring = 0, total = 0;
+    size_t ckpt = 0, seg = 0, lam[2] = {0, 0};
 };
 
 Layout make_layout(const lb_grid_desc *d) {
@@ -117,7 +121,14 @@ Layout make_layout(const lb_grid_desc *d) {
         L.frow = take(((size_t)g.nyf + 1) * 4);
         L.fxs = take((size_t)std::max(d->max_receivers, 1) * 4);
         L.fslot = take((size_t)std::max(d->max_receivers, 1) * 4);
-        L.snap = take(5 * (size_t)g.nsnap * ts);
+        L.snap = take(2 * 5 * (size_t)g.nsnap * ts);   // ping-pong by coarse time parity
+        L.ring = take(2 * 5 * (size_t)g.nring * ts);   // fine outer ring at T+1, T+2
+    }
+    if (d->ckpt_every > 0) {
+        L.ckpt = take((size_t)d->ckpt_capacity * d->lattice * L.pstride * ss);
+        L.seg = take((size_t)d->ckpt_every * n * ts);
+        L.lam[0] = take((size_t)d->lattice * L.pstride * ts);
+        L.lam[1] = take((size_t)d->lattice * L.pstride * ts);
     }
     L.total = off;
     return L;
@@ -153,6 +164,7 @@ struct lb_grid {
     bool patch = false;
     PatchGeom geom;
     void *snap = nullptr;
+    void *ring = nullptr;              // [2][5][nring] fine outer-ring states
     double *partial = nullptr;
     int32_t *scratch = nullptr;
     int64_t t = 0;
@@ -164,6 +176,13 @@ struct lb_grid {
     uint32_t what = 0;
     double *sum_rho = nullptr;
     int sticky = LB_OK;
+    // adjoint support
+    char *ckpt = nullptr;          // [ckpt_capacity] population states
+    void *seg = nullptr;           // [ckpt_every][ny][nx] recomputed rho
+    void *lam[2] = {nullptr, nullptr};
+    std::vector<char> ckpt_pre;    // slot holds a pre-collision state
+    bool ckpt_valid = false;       // checkpoints describe the run since time 0
+    bool state_lost = false;       // an adjoint overwrote the forward state
 };
 
 namespace {
@@ -183,6 +202,10 @@ int hip_fail(lb_grid *h, hipError_t e) {
 double source_at(const lb_grid *h, int64_t n) {
     if (h->sx < 0 || n < 0 || n >= (int64_t)h->wavelet.size()) return 0.0;
     return h->wavelet[(size_t)n];
+}
+
+void *snap_buffer(const lb_grid *h, int64_t t) {
+    return (char *)h->snap + (size_t)(t & 1) * 5 * h->geom.nsnap * h->tsize;
 }
 
 StepParams base_params(const lb_grid *h, const Lattice &g, bool is_main) {
@@ -216,13 +239,32 @@ void attach_receivers(const lb_grid *h, const Lattice &g, StepParams &p, int64_t
 
 // Launch one update of lattice g: pull-stream + collide (or collide only
 // when `pull` is false, for the state at time 0).  Records column `col`.
-int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, bool record, bool sum) {
+// A fine launch takes its outer ring from ring_buf and, with `restr`, also
+// writes the coarse inner ring.
+int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, bool record, bool sum,
+                  const void *ring_buf = nullptr, const InterfaceParams *restr = nullptr) {
     StepParams p = base_params(h, g, is_main);
     p.src = g.curp();
     p.dst = g.prevp();
     if (is_main) p.s_n = source_at(h, col);
     if (record) attach_receivers(h, g, p, col);
     if (sum) p.partial = h->partial;
+    if (is_main && h->patch) {   // keep g(col) on the ring line: snapshot of time col
+        p.snap = snap_buffer(h, col);
+        p.snap_x0 = h->geom.X0;
+        p.snap_y0 = h->geom.Y0;
+        p.snap_w = h->geom.W;
+        p.snap_h = h->geom.H;
+        p.snap_n = h->geom.nsnap;
+    }
+    if (ring_buf) {
+        p.ring_buf = ring_buf;
+        p.ring_n = h->geom.nring;
+    }
+    if (restr) {
+        p.restrict_on = 1;
+        p.iface = *restr;
+    }
     LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
     if (sum) {
         const int64_t nb = lbw::step_blocks(h->storage, g.nx, g.ny, pull);
@@ -252,28 +294,34 @@ lbw::GridRef ref_prev(const Lattice &g) {
     return r;
 }
 
-// Overwrite the fine outer ring (post-collision buffer `cur`) from the coarse
-// state held in the coarse `prev` buffer: a_snap * snapshot + a_now * coarse.
-int prolong(lb_grid *h, double a_snap, double a_now) {
+// Outer-ring states of the fine grid for the two fine steps of the coarse
+// step from T = t_snap: R_{1/2} of the coarse state interpolated along the
+// edges, at T+1 (mean of the ring-line snapshot of T and `coarse`, the
+// coarse state of T+2) and at T+2 (`coarse`), then the fine collision.
+int prolong_pair(lb_grid *h, const lbw::GridRef &coarse, int64_t t_snap) {
     InterfaceParams p = iface_base(h);
-    p.coarse = ref_prev(h->main);
-    p.a_snap = a_snap;
-    p.a_now = a_now;
-    p.dst = h->fine.curp();
+    p.coarse = coarse;
+    p.snap = snap_buffer(h, t_snap);
     p.dst_c2 = h->fine.c2;
     p.dst_nx = h->fine.nx;
     p.dst_ny = h->fine.ny;
     p.dst_pstride = h->fine.pstride;
     p.f = 0.5;
-    LB_TRY(h, lbw::launch_prolong(h->storage, p, h->stream));
+    p.ring_out = h->ring;
+    LB_TRY(h, lbw::launch_prolong_pair(h->storage, p, h->stream));
     return LB_OK;
 }
 
-// Overwrite the coarse inner ring (post-collision buffer `cur`) from the
-// coincident fine nodes of the state held in the fine `prev` buffer.
-int restrict_ring(lb_grid *h) {
+// Half k (0: T+1, 1: T+2) of the ring states made by prolong_pair.
+const void *ring_half(const lb_grid *h, int k) {
+    return (const char *)h->ring + (size_t)k * 5 * h->geom.nring * h->tsize;
+}
+
+// Restriction at the coarse inner ring, fused into a fine launch: R_2 of the
+// coincident fine node's pre-collision state, then the coarse collision,
+// written into the coarse post-collision buffer `cur`.
+InterfaceParams restrict_params(const lb_grid *h) {
     InterfaceParams p = iface_base(h);
-    p.fine = ref_prev(h->fine);
     p.dst = h->main.curp();
     p.dst_c2 = h->main.c2;
     p.dst_nx = h->main.nx;
@@ -282,27 +330,37 @@ int restrict_ring(lb_grid *h) {
     p.f = 2.0;
     p.sponge_width = h->d.sponge_width;
     p.sponge_smax = h->d.sponge_sigma_max;
-    LB_TRY(h, lbw::launch_restrict(h->storage, p, h->stream));
-    return LB_OK;
-}
-
-int snapshot(lb_grid *h) {
-    InterfaceParams p = iface_base(h);
-    p.coarse = ref_prev(h->main);
-    LB_TRY(h, lbw::launch_snapshot(h->storage, p, h->stream));
-    return LB_OK;
+    return p;
 }
 
 bool recording(const lb_grid *h) { return h->nrec > 0 && h->traces; }
 
+size_t state_bytes_main(const lb_grid *h) { return (size_t)h->q * h->main.pstride * h->ssize; }
+
+// Save the state needed to restart the forward run at time `tc`: the buffer
+// the next launch pulls from (post-collision h(tc-1), or g(0) when pre).
+int save_checkpoint(lb_grid *h, int64_t tc, bool pre) {
+    const int64_t slot = tc / h->d.ckpt_every;
+    LB_TRY(h, lbw::launch_copy(h->ckpt + (size_t)slot * state_bytes_main(h), h->main.curp(), state_bytes_main(h),
+                               h->stream));
+    h->ckpt_pre[(size_t)slot] = pre ? 1 : 0;
+    return LB_OK;
+}
+
 int initial_collision(lb_grid *h) {
     int rc;
     const bool rec = recording(h), sum = h->sum_rho != nullptr;
+    if (h->d.ckpt_every > 0) {
+        h->ckpt_valid = h->t == 0;
+        if (h->ckpt_valid && (rc = save_checkpoint(h, 0, true))) return rc;
+    }
     if ((rc = launch_update(h, h->main, true, false, h->t, rec, sum))) return rc;
     if (h->patch) {
-        if ((rc = launch_update(h, h->fine, false, false, h->t, rec, false))) return rc;
-        if ((rc = prolong(h, 0.0, 1.0))) return rc;
-        if ((rc = restrict_ring(h))) return rc;
+        // fine state of time 0 with its outer ring from the coarse state
+        // g(0) (second half of the pair), and the coarse inner ring from it
+        if ((rc = prolong_pair(h, ref_prev(h->main), h->t))) return rc;
+        const InterfaceParams rp = restrict_params(h);
+        if ((rc = launch_update(h, h->fine, false, false, h->t, rec, false, ring_half(h, 1), &rp))) return rc;
     }
     h->collided = true;
     return LB_OK;
@@ -313,18 +371,21 @@ int one_step(lb_grid *h) {
     const bool rec = recording(h), sum = h->sum_rho != nullptr;
     const int64_t col = h->t + 1;
     if (!h->patch) {
+        if (h->ckpt_valid && col % h->d.ckpt_every == 0 && (rc = save_checkpoint(h, col, false))) return rc;
         if ((rc = launch_update(h, h->main, true, true, col, rec, sum))) return rc;
         h->t = col;
         return LB_OK;
     }
-    // Coarse step T -> T+2 in fine time units (Sec. IV schedule).
-    if ((rc = snapshot(h))) return rc;                                  // coarse ring at T
-    if ((rc = launch_update(h, h->main, true, true, col, rec, false))) return rc;   // coarse to T+2
-    if ((rc = launch_update(h, h->fine, false, true, col, false, false))) return rc; // fine to T+1
-    if ((rc = prolong(h, 0.5, 0.5))) return rc;                         // ring at T+1
-    if ((rc = launch_update(h, h->fine, false, true, col, rec, false))) return rc;  // fine to T+2
-    if ((rc = prolong(h, 0.0, 1.0))) return rc;                         // ring at T+2
-    if ((rc = restrict_ring(h))) return rc;                             // coarse ring at T+2
+    // Coarse step T -> T+2 in fine time units (Sec. IV schedule), 4 launches:
+    // the coarse step (also keeps the ring-line snapshot of T+2 for the next
+    // step), the fine outer-ring states of T+1 and T+2 from the coarse
+    // state, and two fine steps; the second also restricts to the coarse
+    // inner ring of T+2.
+    if ((rc = launch_update(h, h->main, true, true, col, rec, false))) return rc;     // coarse to T+2
+    if ((rc = prolong_pair(h, ref_prev(h->main), h->t))) return rc;                  // h(T): pulled = g(T+2)
+    if ((rc = launch_update(h, h->fine, false, true, col, false, false, ring_half(h, 0)))) return rc;  // T+1
+    const InterfaceParams rp = restrict_params(h);
+    if ((rc = launch_update(h, h->fine, false, true, col, rec, false, ring_half(h, 1), &rp))) return rc;  // T+2
     h->t = col;
     return LB_OK;
 }
@@ -388,6 +449,8 @@ int set_state_impl(lb_grid *h, Lattice &g, const void *rho, const void *jx, cons
     if (&g == &h->main) {
         h->t = 0;
         h->collided = false;
+        h->state_lost = false;
+        h->ckpt_valid = false;
         if (h->patch) {   // the fine grid restarts at rest (lb_set_state_fine may follow)
             Lattice &f = h->fine;
             f.cur = 0;
@@ -552,6 +615,14 @@ int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes, vo
         f.rxs = (int32_t *)(h->ws + L.fxs);
         f.rslot = (int32_t *)(h->ws + L.fslot);
         h->snap = h->ws + L.snap;
+        h->ring = h->ws + L.ring;
+    }
+    if (d->ckpt_every > 0) {
+        h->ckpt = h->ws + L.ckpt;
+        h->seg = h->ws + L.seg;
+        h->lam[0] = h->ws + L.lam[0];
+        h->lam[1] = h->ws + L.lam[1];
+        h->ckpt_pre.assign((size_t)d->ckpt_capacity, 0);
     }
     // the state starts at rest: zero both population buffers of each grid
     hipError_t e = lbw::launch_fill_zero(m.pop[0], (int64_t)zero_bytes, h->stream);
@@ -664,8 +735,9 @@ int lb_step_n(lb_grid *h, int64_t n) {
     if (!h) return LB_E_INVALID;
     if (h->sticky) return h->sticky;
     if (n < 0) return LB_E_RANGE;
-    if (!h->main.medium || (h->patch && !h->fine.medium)) return LB_E_STATE;
+    if (!h->main.medium || (h->patch && !h->fine.medium) || h->state_lost) return LB_E_STATE;
     if ((recording(h) || h->sum_rho) && h->t + n >= h->d.trace_capacity) return LB_E_RANGE;
+    if (h->d.ckpt_every > 0 && (h->t + n) / h->d.ckpt_every >= h->d.ckpt_capacity) return LB_E_RANGE;
     int rc;
     if (!h->collided && (rc = initial_collision(h))) return rc;
     for (int64_t k = 0; k < n; ++k)
@@ -754,8 +826,95 @@ int lb_set_raw_state(lb_grid *h, const void *d_in) {
     LB_TRY(h, hipStreamSynchronize(h->stream));
     h->t = hd.t;
     h->collided = hd.collided != 0;
+    h->state_lost = false;
+    h->ckpt_valid = false;       // checkpoints of another run do not apply
     h->main.prev_pre = hd.main_prev_pre;
     h->fine.prev_pre = hd.fine_prev_pre;
+    return LB_OK;
+}
+
+int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res, double *d_phi) {
+    if (!h || !d_obs || !d_res || !d_phi) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (!recording(h) || !(h->what & LB_FIELD_P)) return LB_E_STATE;
+    if (nt < 0 || nt >= h->d.trace_capacity) return LB_E_RANGE;
+    LB_TRY(h, lbw::launch_misfit(h->storage, h->traces, d_obs, d_res, h->nrec, h->d.trace_capacity, nt + 1, d_phi,
+                                 h->stream));
+    return LB_OK;
+}
+
+int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
+    if (!h || !d_res || !d_grad) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (h->patch) return LB_E_UNSUPPORTED;
+    if (h->d.ckpt_every <= 0) return LB_E_STATE;
+    if (!h->collided || !h->ckpt_valid || h->state_lost || nt != h->t) return LB_E_STATE;
+    if (!recording(h)) return LB_E_STATE;
+    const int64_t K = h->d.ckpt_every;
+    Lattice &g = h->main;
+    const int64_t n_nodes = (int64_t)g.nx * g.ny;
+    const size_t tsz = h->tsize;
+
+    lbw::AdjointParams ap;
+    ap.c2 = g.c2;
+    ap.grad = d_grad;
+    ap.nx = g.nx;
+    ap.ny = g.ny;
+    ap.pstride = g.pstride;
+    ap.q = h->q;
+    ap.coll = h->coll;
+    if (h->q == 5) {
+        const double dw[5] = {-2.0, 0.5, 0.5, 0.5, 0.5};
+        for (int i = 0; i < 5; ++i) ap.dw[i] = dw[i];
+    } else {
+        const double r = h->d.d2q9_ratio, a = 1.0 / (2.0 + 4.0 * r);
+        ap.dw[0] = -4.0 * a - 4.0 * r * a;
+        for (int i = 1; i < 9; ++i) ap.dw[i] = i <= 4 ? a : r * a;
+    }
+    ap.sponge_width = h->d.sponge_width;
+    ap.sponge_smax = h->d.sponge_sigma_max;
+    ap.src_x = h->sx;
+    ap.src_y = h->sy;
+    if (g.has_rec) {
+        ap.rec.row_ptr = g.rrow;
+        ap.rec.xs = g.rxs;
+        ap.rec.slot = g.rslot;
+    }
+    ap.rec.traces = const_cast<void *>(d_res);
+    ap.rec.nslots = h->nrec;
+    ap.rec.cap = h->d.trace_capacity;
+
+    LB_TRY(h, lbw::launch_fill_zero(d_grad, n_nodes * 8, h->stream));
+    int cur_lam = 0;     // lam[cur_lam] holds lambda(n+1)
+    for (int64_t j = nt / K; j >= 0; --j) {
+        const int64_t a = j * K, b = std::min(a + K - 1, nt);
+        // restore the forward state that the launch of time a pulls from
+        LB_TRY(h, lbw::launch_copy(g.pop[0], h->ckpt + (size_t)j * state_bytes_main(h), state_bytes_main(h),
+                                   h->stream));
+        g.cur = 0;
+        for (int64_t m = a; m <= b; ++m) {
+            const bool pull = !(m == a && h->ckpt_pre[(size_t)j]);
+            StepParams p = base_params(h, g, true);
+            p.src = g.curp();
+            p.dst = g.prevp();
+            p.s_n = source_at(h, m);
+            p.rho_out = (char *)h->seg + (size_t)(m - a) * n_nodes * tsz;
+            LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
+            g.cur = 1 - g.cur;
+        }
+        for (int64_t n = b; n >= a; --n) {
+            ap.rho = (char *)h->seg + (size_t)(n - a) * n_nodes * tsz;
+            ap.terminal = n == nt;
+            ap.initial = n == 0;
+            ap.lam_next = h->lam[cur_lam];
+            ap.lam = h->lam[1 - cur_lam];
+            ap.s_n = source_at(h, n);
+            ap.rec.col = n;
+            LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
+            cur_lam = 1 - cur_lam;
+        }
+    }
+    h->state_lost = true;
     return LB_OK;
 }
 

@@ -247,3 +247,28 @@ def serving_wavelet(req):
     """Ricker wavelet at fc = c_min / 20 (>= 20 nodes per wavelength), from
     the request's speed bound so that no device read is needed."""
     return ricker_wavelet(req["nsteps"] + 1, serving_min_speed(req) / 20.0)
+
+
+# ---------------------------------------------------------------------------
+# adjoint workload: a multi-shot gradient of the trace misfit
+# ---------------------------------------------------------------------------
+def adjoint_workload(n=2048, nshots=16, nsteps=3000, nrec=128, seed=55, smooth=32.0):
+    """True medium: 5 layers with speeds increasing 0.3 -> 0.55 with depth
+    plus 20 seeded +-10 % anomalies; starting medium: the true one smoothed by
+    a Gaussian of `smooth` nodes.  Sources on row 64 at x = 64 + (k + 1/2) *
+    (n - 128) / nshots; shared receivers on row 64; fc = c_min / 20."""
+    from scipy import ndimage
+    speeds = np.linspace(0.3, 0.55, 5)
+    layer = np.minimum((np.arange(n) * 5) // n, 4)
+    c = speeds[layer][:, None] * np.ones((1, n))
+    s = n / 4096.0
+    c = _add_anomalies(c, 20, seed, margin=max(2.0, 64.0 * s), sig_lo=max(1.0, 32.0 * s),
+                       sig_hi=max(2.0, 128.0 * s))
+    c0 = ndimage.gaussian_filter(c, sigma=smooth * n / 2048.0, mode="nearest")
+    L = 64 if n >= 1024 else max(4, n // 16)
+    fc = float(min(c.min(), c0.min())) / 20.0
+    xs = [int(L + (k + 0.5) * (n - 2 * L) / nshots) for k in range(nshots)]
+    return {"nx": n, "ny": n, "c2_true": c * c, "c2_init": c0 * c0, "nsteps": nsteps,
+            "sources": [(x, L) for x in xs], "receivers": surface_receivers(n, nrec, L, L),
+            "sponge_width": L, "sponge_sigma_max": 0.1, "fc": fc,
+            "wavelet": ricker_wavelet(nsteps + 1, fc)}

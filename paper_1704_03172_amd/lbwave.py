@@ -33,7 +33,7 @@ EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_workspace_bytes",
            "lb_status_string", "lb_device_copy",
            "lb_batch_workspace_bytes", "lb_batch_create", "lb_shot_workspace_bytes",
            "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times",
-           "lb_batch_sync", "lb_batch_destroy")
+           "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint")
 
 
 class LBError(RuntimeError):
@@ -57,7 +57,9 @@ class Desc(ctypes.Structure):
         ("patch_refine", ctypes.c_int32),
         ("patch_overlap_out", ctypes.c_int32), ("patch_overlap_in", ctypes.c_int32),
         ("trace_capacity", ctypes.c_int64),
-        ("max_receivers", ctypes.c_int32), ("_pad1", ctypes.c_int32),
+        ("max_receivers", ctypes.c_int32),
+        ("ckpt_every", ctypes.c_int32), ("ckpt_capacity", ctypes.c_int32),
+        ("_pad1", ctypes.c_int32),
     ]
 
 
@@ -120,6 +122,8 @@ def lib():
         "lb_batch_times": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
         "lb_batch_sync": (ctypes.c_int, [vp]),
         "lb_batch_destroy": (ctypes.c_int, [vp]),
+        "lb_misfit": (ctypes.c_int, [vp, vp, i64, vp, vp]),
+        "lb_adjoint": (ctypes.c_int, [vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -137,7 +141,7 @@ def _check(code, what):
 def make_desc(nx, ny, lattice=5, collision="bgk", precision="f32", tau=0.5,
               s=None, ratio=0.25, sponge_width=0, sponge_sigma_max=0.0,
               patch=None, overlap_out=2, overlap_in=2, trace_capacity=0,
-              max_receivers=0):
+              max_receivers=0, ckpt_every=0, ckpt_capacity=0):
     d = Desc()
     lib().lb_default_desc(ctypes.byref(d))
     d.nx, d.ny = int(nx), int(ny)
@@ -157,6 +161,8 @@ def make_desc(nx, ny, lattice=5, collision="bgk", precision="f32", tau=0.5,
         d.patch_overlap_out, d.patch_overlap_in = int(overlap_out), int(overlap_in)
     d.trace_capacity = int(trace_capacity)
     d.max_receivers = int(max_receivers)
+    d.ckpt_every = int(ckpt_every)
+    d.ckpt_capacity = int(ckpt_capacity)
     return d
 
 
@@ -304,6 +310,27 @@ class Grid:
 
     def set_raw_state(self, blob):
         _check(lib().lb_set_raw_state(self.handle, ctypes.c_void_p(blob.data_ptr())), "lb_set_raw_state")
+
+    def misfit(self, d_obs, nt):
+        """(phi, residual) of the recorded pressure traces against d_obs
+        [nrec][trace_capacity] (device tensor of the arithmetic type)."""
+        torch = self._torch
+        d_obs = d_obs.to(device=self.device, dtype=self.dtype).contiguous()
+        res = torch.zeros_like(d_obs)
+        phi = torch.zeros((), dtype=torch.float64, device=self.device)
+        _check(lib().lb_misfit(self.handle, ctypes.c_void_p(d_obs.data_ptr()), int(nt),
+                               ctypes.c_void_p(res.data_ptr()), ctypes.c_void_p(phi.data_ptr())), "lb_misfit")
+        return phi, res
+
+    def adjoint(self, res, nt):
+        """dL/dc^2 [ny][nx] (FP64) for trace sensitivities res
+        [nrec][trace_capacity] after a forward run of nt steps."""
+        torch = self._torch
+        res = res.to(device=self.device, dtype=self.dtype).contiguous()
+        grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _check(lib().lb_adjoint(self.handle, ctypes.c_void_p(res.data_ptr()), int(nt),
+                                ctypes.c_void_p(grad.data_ptr())), "lb_adjoint")
+        return grad
 
     def sync(self):
         _check(lib().lb_sync(self.handle), "lb_sync")
