@@ -98,8 +98,13 @@ struct StepParams {
     const void *ring_buf = nullptr;    // fine grid of a patch: post-collision outer-ring
     int32_t ring_n = 0;                // states [5][ring_n] taken from the coarse grid
     int32_t restrict_on = 0;           // fine grid of a patch: also write the coarse
-    InterfaceParams iface;             // inner ring from this launch's pre-collision
-};                                     // state (iface: as for launch_restrict)
+                                       // inner ring from this launch's pre-collision
+                                       // state (iface: as for launch_restrict)
+    int32_t prolong_on = 0;            // coarse grid of a patch: also compute the fine
+                                       // outer-ring pair (iface: as launch_prolong_pair)
+    InterfaceParams iface;
+    int32_t pre_rows = 0;              // set by launch_step: leading block rows that
+};                                     // do the prolong_on work
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
 // lambda(n) = K^T (1 - sigma) P^T lambda(n+1) + r(n), with the gradient

@@ -347,9 +347,62 @@ __device__ inline void ring_interp(const InterfaceParams &p, int i, int j, typen
     }
 }
 
+// The outer-ring states of the two fine steps of one coarse step T -> T+2,
+// one thread per fine ring node: R_{1/2} of the coarse state interpolated to
+// the node, at T+1 (mean of the ring-line snapshot of T and the coarse state
+// of T+2) and at T+2, each followed by the fine collision.
+template <typename S, int KIND>
+__device__ inline void prolong_pair_node(const InterfaceParams &p, int r) {
+    using T = typename Tr<S>::T;
+    const PatchGeom &g = p.g;
+    if (r >= g.nring) return;
+    int i, j;
+    if (r < g.nxf) { i = r; j = 0; }
+    else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
+    else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
+    else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
+    int nodes_x[4], nodes_y[4], sidx[4];
+    T wt[4];
+    ring_stencil<T>(g, i, j, nodes_x, nodes_y, sidx, wt);
+    // every load of the node up front (one round of memory latency); the
+    // weight-0 entries of a coincident node repeat a valid node
+    T gn[4][5], gs[4][5];
+    const T *snap = reinterpret_cast<const T *>(p.snap);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn[s]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gs[s][q] = snap[q * g.nsnap + sidx[s]];
+    }
+    T mid[5], end[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) mid[q] = end[q] = T(0);
+    const T half = T(0.5);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            mid[q] += wt[s] * (half * gn[s][q] + half * gs[s][q]);
+            end[q] += wt[s] * gn[s][q];
+        }
+    }
+    T *ro = reinterpret_cast<T *>(p.ring_out);
+    T out0[5], out1[5];
+    rescale_collide<S, KIND>(p, mid, i, j, out0);
+    rescale_collide<S, KIND>(p, end, i, j, out1);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        ro[k * g.nring + r] = out0[k];
+        ro[(5 + k) * g.nring + r] = out1[k];
+    }
+}
+
 // ---- fused step -------------------------------------------------------------
 // One thread's share of the update: V consecutive nodes (x0 .. x0+V-1) of row
 // y.  Returns the FP64 sum of rho over them when p.partial is set.
+template <typename S>
+constexpr bool kIsF64 = sizeof(S) == 8;
+
 template <typename S, int Q, int KIND, bool PULL>
 __device__ inline double update_tile(const StepParams &p, int x0, int y) {
     using T = typename Tr<S>::T;
@@ -484,7 +537,17 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
 template <typename S, int Q, int KIND, bool PULL>
 __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
     constexpr int V = PULL ? Tr<S>::V : 1;
-    const int y = blockIdx.y;
+    if constexpr (Q == 5 && !kIsF64<S>) {
+        // leading block rows of a coarse launch: the fine outer-ring states
+        // of this coarse step (they read only what this launch reads; FP64
+        // runs them as a launch of their own, whose registers would lower
+        // this kernel's occupancy)
+        if ((int)blockIdx.y < p.pre_rows) {
+            prolong_pair_node<S, KIND>(p.iface, ((int)blockIdx.y * gridDim.x + blockIdx.x) * kStepBlock + threadIdx.x);
+            return;
+        }
+    }
+    const int y = blockIdx.y - p.pre_rows;
     const int x0 = (blockIdx.x * kStepBlock + threadIdx.x) * V;
     double local = update_tile<S, Q, KIND, PULL>(p, x0, y);
 
@@ -497,7 +560,7 @@ __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < kStepBlock / 64; ++k) s += sh[k];
-            p.partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+            p.partial[(int64_t)y * gridDim.x + blockIdx.x] = s;
         }
     }
 }
@@ -840,55 +903,9 @@ __global__ __launch_bounds__(kBlock) void k_restrict(InterfaceParams p) {
     rescale_collide_store_impl<S, KIND>(p, gf, x, y);
 }
 
-// The outer-ring states of the two fine steps of one coarse step T -> T+2,
-// one thread per fine ring node: R_{1/2} of the coarse state interpolated to
-// the node, at T+1 (mean of the ring-line snapshot of T and the coarse state
-// of T+2) and at T+2, each followed by the fine collision.
 template <typename S, int KIND>
 __global__ __launch_bounds__(kBlock) void k_prolong_pair(InterfaceParams p) {
-    using T = typename Tr<S>::T;
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    const PatchGeom &g = p.g;
-    if (r >= g.nring) return;
-    int i, j;
-    if (r < g.nxf) { i = r; j = 0; }
-    else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
-    else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
-    else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
-    int nodes_x[4], nodes_y[4], sidx[4];
-    T wt[4];
-    ring_stencil<T>(g, i, j, nodes_x, nodes_y, sidx, wt);
-    // every load of the node up front (one round of memory latency); the
-    // weight-0 entries of a coincident node repeat a valid node
-    T gn[4][5], gs[4][5];
-    const T *snap = reinterpret_cast<const T *>(p.snap);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn[s]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) gs[s][q] = snap[q * g.nsnap + sidx[s]];
-    }
-    T mid[5], end[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) mid[q] = end[q] = T(0);
-    const T half = T(0.5);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            mid[q] += wt[s] * (half * gn[s][q] + half * gs[s][q]);
-            end[q] += wt[s] * gn[s][q];
-        }
-    }
-    T *ro = reinterpret_cast<T *>(p.ring_out);
-    T out0[5], out1[5];
-    rescale_collide<S, KIND>(p, mid, i, j, out0);
-    rescale_collide<S, KIND>(p, end, i, j, out1);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        ro[k * g.nring + r] = out0[k];
-        ro[(5 + k) * g.nring + r] = out1[k];
-    }
+    prolong_pair_node<S, KIND>(p, blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---- dispatch helpers ----------------------------------------------------------
@@ -898,10 +915,25 @@ template <typename S>
 int vwidth(bool pull) { return pull ? Tr<S>::V : 1; }
 
 template <typename S>
-hipError_t step_dispatch(const StepParams &p, bool pull, hipStream_t s) {
+hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
     const int V = vwidth<S>(pull);
-    dim3 grid((unsigned)(((int64_t)p.nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)), (unsigned)p.ny);
-    const int kind = p.coll.kind;
+    dim3 grid((unsigned)(((int64_t)p0.nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)), (unsigned)p0.ny);
+    const int kind = p0.coll.kind;
+    StepParams p = p0;
+    p.pre_rows = 0;
+    if (p0.prolong_on) {
+        const int64_t per_row = (int64_t)grid.x * kStepBlock;
+        const int rows = (int)((p0.iface.g.nring + per_row - 1) / per_row);
+        if (!kIsF64<S> && (int64_t)p0.ny + rows <= 65535) {
+            p.pre_rows = rows;
+            grid.y += (unsigned)rows;
+        } else {   // a launch of its own first
+            const bool mrt = kind == 1;
+            dim3 pg(blocks_for(p0.iface.g.nring));
+            if (mrt) hipLaunchKernelGGL((k_prolong_pair<S, 1>), pg, dim3(kBlock), 0, s, p0.iface);
+            else hipLaunchKernelGGL((k_prolong_pair<S, 0>), pg, dim3(kBlock), 0, s, p0.iface);
+        }
+    }
 #define LBW_LAUNCH(QQ, KK, PP) \
     hipLaunchKernelGGL((k_step<S, QQ, KK, PP>), grid, dim3(kStepBlock), 0, s, p)
     if (p.q == 5) {

@@ -240,9 +240,11 @@ void attach_receivers(const lb_grid *h, const Lattice &g, StepParams &p, int64_t
 // Launch one update of lattice g: pull-stream + collide (or collide only
 // when `pull` is false, for the state at time 0).  Records column `col`.
 // A fine launch takes its outer ring from ring_buf and, with `restr`, also
-// writes the coarse inner ring.
+// writes the coarse inner ring; a coarse launch with `pro` also computes the
+// fine outer-ring pair.
 int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, bool record, bool sum,
-                  const void *ring_buf = nullptr, const InterfaceParams *restr = nullptr) {
+                  const void *ring_buf = nullptr, const InterfaceParams *restr = nullptr,
+                  const InterfaceParams *pro = nullptr) {
     StepParams p = base_params(h, g, is_main);
     p.src = g.curp();
     p.dst = g.prevp();
@@ -264,6 +266,9 @@ int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, 
     if (restr) {
         p.restrict_on = 1;
         p.iface = *restr;
+    } else if (pro) {
+        p.prolong_on = 1;
+        p.iface = *pro;
     }
     LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
     if (sum) {
@@ -298,7 +303,7 @@ lbw::GridRef ref_prev(const Lattice &g) {
 // step from T = t_snap: R_{1/2} of the coarse state interpolated along the
 // edges, at T+1 (mean of the ring-line snapshot of T and `coarse`, the
 // coarse state of T+2) and at T+2 (`coarse`), then the fine collision.
-int prolong_pair(lb_grid *h, const lbw::GridRef &coarse, int64_t t_snap) {
+InterfaceParams prolong_params(lb_grid *h, const lbw::GridRef &coarse, int64_t t_snap) {
     InterfaceParams p = iface_base(h);
     p.coarse = coarse;
     p.snap = snap_buffer(h, t_snap);
@@ -308,8 +313,7 @@ int prolong_pair(lb_grid *h, const lbw::GridRef &coarse, int64_t t_snap) {
     p.dst_pstride = h->fine.pstride;
     p.f = 0.5;
     p.ring_out = h->ring;
-    LB_TRY(h, lbw::launch_prolong_pair(h->storage, p, h->stream));
-    return LB_OK;
+    return p;
 }
 
 // Half k (0: T+1, 1: T+2) of the ring states made by prolong_pair.
@@ -358,7 +362,7 @@ int initial_collision(lb_grid *h) {
     if (h->patch) {
         // fine state of time 0 with its outer ring from the coarse state
         // g(0) (second half of the pair), and the coarse inner ring from it
-        if ((rc = prolong_pair(h, ref_prev(h->main), h->t))) return rc;
+        LB_TRY(h, lbw::launch_prolong_pair(h->storage, prolong_params(h, ref_prev(h->main), h->t), h->stream));
         const InterfaceParams rp = restrict_params(h);
         if ((rc = launch_update(h, h->fine, false, false, h->t, rec, false, ring_half(h, 1), &rp))) return rc;
     }
@@ -376,13 +380,21 @@ int one_step(lb_grid *h) {
         h->t = col;
         return LB_OK;
     }
-    // Coarse step T -> T+2 in fine time units (Sec. IV schedule), 4 launches:
-    // the coarse step (also keeps the ring-line snapshot of T+2 for the next
-    // step), the fine outer-ring states of T+1 and T+2 from the coarse
-    // state, and two fine steps; the second also restricts to the coarse
-    // inner ring of T+2.
-    if ((rc = launch_update(h, h->main, true, true, col, rec, false))) return rc;     // coarse to T+2
-    if ((rc = prolong_pair(h, ref_prev(h->main), h->t))) return rc;                  // h(T): pulled = g(T+2)
+    // Coarse step T -> T+2 in fine time units (Sec. IV schedule), 3 launches:
+    // the coarse step, which also keeps the ring-line snapshot of T+2 for the
+    // next step and computes the fine outer-ring states of T+1 and T+2 (from
+    // h(T), whose pull is g(T+2), and the snapshot of T: both only read by
+    // this launch); then two fine steps, the second of which also restricts
+    // to the coarse inner ring of T+2.
+    lbw::GridRef coarse_src;
+    coarse_src.pop = h->main.curp();
+    coarse_src.pre = 0;
+    coarse_src.c2 = h->main.c2;
+    coarse_src.nx = h->main.nx;
+    coarse_src.ny = h->main.ny;
+    coarse_src.pstride = h->main.pstride;
+    const InterfaceParams pp = prolong_params(h, coarse_src, h->t);
+    if ((rc = launch_update(h, h->main, true, true, col, rec, false, nullptr, nullptr, &pp))) return rc;
     if ((rc = launch_update(h, h->fine, false, true, col, false, false, ring_half(h, 0)))) return rc;  // T+1
     const InterfaceParams rp = restrict_params(h);
     if ((rc = launch_update(h, h->fine, false, true, col, rec, false, ring_half(h, 1), &rp))) return rc;  // T+2
