@@ -4,13 +4,19 @@ Workload (default): the 4096 x 4096 two-layer medium with 20 seeded +-10 %
 anomalies, 64-node sponge, Ricker source at >= 20 nodes per wavelength and
 256 surface receivers; D2Q5, BGK tau = 1/2, FP32 populations.  One "step" is
 one time step of the whole grid (pull-stream, moments, per-node weights,
-linear equilibrium, collision, source, sponge, receiver sampling: one fused
-kernel launch).  Inputs are resident in HBM before the timed region.
+linear equilibrium, collision, source, sponge, receiver sampling at every
+time).  lb_step_n runs two steps per fused launch (the last launch of a call
+takes one), so the dominant kernel is the two-step kernel: it reads h(n)
+and writes h(n+2), 44 algorithmic bytes per node per launch (24 read, 20
+written), i.e. 22 bytes per lattice update.  Inputs are resident in HBM
+before the timed region.
 
-Prints ONE JSON line: MLUPS (value), roofline of the step kernel (44
-algorithmic bytes per lattice update against the 8 TB/s HBM peak), a
-measured device-copy bandwidth, comparison variants (MRT, D2Q9, FP64,
-refinement) and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line: MLUPS (value), roofline of the two-step kernel (its
+launch duration measured with HIP events as the difference of two runs that
+differ only in the number of two-step launches, against the 8 TB/s HBM
+peak), a measured device-copy bandwidth, comparison variants (MRT, D2Q9,
+FP64, FP16 storage, refinement), the adjoint and serving measurements and
+the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -28,9 +34,21 @@ METRIC = "D2Q5 FP32 MLUPS & % HBM roofline; served shots/s with p50/p99 latency"
 
 
 def bytes_per_lup(q, precision):
+    """Algorithmic bytes per node per launch: Q populations read and written,
+    c^2 read."""
     s = {"f32": 4, "f64": 8, "f16s": 2}[precision]
     c = 8 if precision == "f64" else 4
     return 2 * q * s + c
+
+
+def launch_counts(nsteps):
+    """(two-step launches, one-step launches) of one lb_step_n(nsteps) call
+    on a grid without patch, sum-of-rho recording or checkpoints: two-step
+    launches while at least three steps remain."""
+    k = 0
+    while nsteps - k >= 3:
+        k += 2
+    return k // 2, nsteps - k
 
 
 def log(msg):
@@ -163,7 +181,7 @@ def measured_traffic():
     (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or None when
     the kernel source changed after the counters were taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "k_step_d2q5_bgk_f32_layered4096_hbm_counters.md")
+    prof = os.path.join(ROOT, "profiles", "k_step2_d2q5_bgk_f32_layered4096_hbm_counters.md")
     src = os.path.join(ROOT, "paper_1704_03172_amd", "csrc", "lb_kernels.hip")
     try:
         text = open(prof).read()
@@ -238,11 +256,16 @@ def main():
     N = wl["nx"] * wl["ny"]
     cap = steps + warmup + 1
 
-    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap)
+    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + 2 * 401 + 2 * 101)
     log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
     t = time_steps(torch, grid, steps, warmup)
     mlups = N * steps / t / 1e6
-    kern_s = t / steps
+    n2, n1 = launch_counts(steps)
+    # the two-step kernel's launch duration: two calls that differ only in
+    # their number of two-step launches (400 vs 100, one one-step launch each)
+    ta = time_steps(torch, grid, 2 * 400 + 1, 0)
+    tb = time_steps(torch, grid, 2 * 100 + 1, 0)
+    kern_s = (ta - tb) / 300
     bpl = bytes_per_lup(5, "f32")
     achieved = bpl * N / kern_s / 1e9
     tr = grid.traces[0].cpu().numpy()
@@ -262,11 +285,13 @@ def main():
             g = make_layered(lbwave, wl, q, coll, prec, vsteps + 11)
             tv = time_steps(torch, g, vsteps, 10)
             b = bytes_per_lup(q, prec)
+            nb = b * N * sum(launch_counts(vsteps))      # algorithmic bytes of the launches
             variants["D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())] = {
                 "MLUPS": round(N * vsteps / tv / 1e6, 1),
-                "GBs": round(b * N * vsteps / tv / 1e9, 1),
-                "frac_hbm": round(b * N * vsteps / tv / 1e9 / HBM_PEAK_GBS, 4),
-                "bytes_per_lup": b, "steps": vsteps}
+                "GBs": round(nb / tv / 1e9, 1),
+                "frac_hbm": round(nb / tv / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_node_per_launch": b, "steps": vsteps,
+                "launches_two_step_one_step": list(launch_counts(vsteps))}
             log("variant %s %.0f MLUPS" % (list(variants)[-1], N * vsteps / tv / 1e6))
             g.close()
             del g
@@ -313,8 +338,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-                     "kernel": "k_step<float,5,BGK,pull>", "bytes_per_lup": bpl,
+                     "kernel": "k_step2<float,5,BGK> (two steps per launch)",
+                     "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": 2 * N,
                      "avg_kernel_us": round(kern_s * 1e6, 3)},
+        "launches_two_step_one_step": [n2, n1],
         "copy_kernel_GBs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "traces_finite": finite,

@@ -107,6 +107,12 @@ typedef struct lb_grid lb_grid;
  *                  workspace grows by ckpt_capacity states, K rho fields and
  *                  two adjoint population sets).  0: no checkpoints.
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
+ *   steps_per_launch  0 (default): lb_step_n advances two time steps per
+ *                  kernel launch wherever it can (no patch, no sum-rho
+ *                  recording, no checkpoint falling between the two; the
+ *                  last launch of each call takes one step), which halves
+ *                  the HBM traffic per step; the results equal those of one
+ *                  step per launch bit for bit.  1: one step per launch.
  *   nbatch         independent shots sharing the grid shape (must be 1).
  */
 typedef struct {
@@ -129,12 +135,12 @@ typedef struct {
     int32_t max_receivers;
     int32_t ckpt_every;
     int32_t ckpt_capacity;
-    int32_t _pad1;
+    int32_t steps_per_launch;
 } lb_grid_desc;
 
 /* Fill *d with defaults: 64 x 64 D2Q5 BGK FP32, tau = 1/2, MRT rates
  * (1, 1, 1, 2, 2, 2, 1, 1, 2), ratio 1/4, no sponge, no patch,
- * trace_capacity 0, max_receivers 0, nbatch 1. */
+ * trace_capacity 0, max_receivers 0, steps_per_launch 0, nbatch 1. */
 void lb_default_desc(lb_grid_desc *d);
 
 /* Check a descriptor without a GPU.  Returns LB_OK or the error code that

@@ -104,7 +104,9 @@ struct StepParams {
                                        // outer-ring pair (iface: as launch_prolong_pair)
     InterfaceParams iface;
     int32_t pre_rows = 0;              // set by launch_step: leading block rows that
-};                                     // do the prolong_on work
+                                       // do the prolong_on work
+    double s_n2 = 0.0;                 // launch_step2: source amplitude of the second step
+};
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
 // lambda(n) = K^T (1 - sigma) P^T lambda(n+1) + r(n), with the gradient
@@ -184,6 +186,13 @@ hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t 
 hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
+// Two pull steps in one launch: reads h(n) from p.src, writes h(n+2) to
+// p.dst (a buffer other than p.src), records columns p.rec.col and
+// p.rec.col + 1, source amplitudes p.s_n and p.s_n2.  No reduction
+// partials, rho_out, snapshot or interface work.
+hipError_t launch_step2(int storage, const StepParams &p, hipStream_t s);
+int step2_owned_columns(int storage);
+bool step2_supported(int storage, int q);   // configurations the two-step kernel serves
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
                                double *out, hipStream_t s);

@@ -21,7 +21,16 @@
 // this 11-stream pattern, and +7 % for a plain copy).
 #include "lb_internal.h"
 
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
+
+// No automatic a*b+c contraction in this file: where the compiler forms fused
+// multiply-adds depends on the surrounding code, so the same per-node
+// arithmetic inlined into different kernels (one step per launch, two steps
+// per launch, the batched executor) could round differently.  The fused
+// multiply-adds of the collision are written out (fmaT) instead.
+#pragma clang fp contract(off)
 
 namespace lbw {
 namespace {
@@ -79,6 +88,23 @@ template <> struct Tr<_Float16> {
     static constexpr int V = 8;
     typedef _Float16 vec __attribute__((ext_vector_type(8), aligned(2)));
 };
+
+// Conversion of a computed value to the storage format.  For FP16 storage
+// the value is first materialised in FP32 (the empty asm is a value barrier):
+// otherwise the compiler may fold the last multiply and the conversion into
+// one mixed-precision FMA (a single rounding) in some kernels and not in
+// others, and a state stored by different kernels would differ in its bits.
+template <typename S, typename T>
+__device__ inline S to_store(T v) {
+    if constexpr (sizeof(S) < sizeof(T)) asm volatile("" : "+v"(v));
+    return S(v);
+}
+
+template <typename T>
+__device__ inline T fmaT(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
 
 __device__ inline int wrapi(int v, int n) {
     v %= n;
@@ -153,13 +179,13 @@ __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&ou
     for (int i = 0; i < Q; ++i) {
         T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
         T cj = T(cxv<Q>(i)) * jx + T(cyv<Q>(i)) * jy;
-        T geq = w[i] * rho + (i == 0 ? T(0) : kj * cj);
+        T geq = fmaT(w[i], rho, i == 0 ? T(0) : kj * cj);
         d[i] = g[i] - geq;
     }
     if (KIND == 0) {
         const T om = T(c.omega);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) out[i] = g[i] - om * d[i];
+        for (int i = 0; i < Q; ++i) out[i] = fmaT(-om, d[i], g[i]);
     } else {
         T r[9];
 #pragma unroll
@@ -204,6 +230,43 @@ __device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, 
     if (rc.what & 2u) { tr[f * plane + base] = rho; ++f; }
     if (rc.what & 4u) { tr[f * plane + base] = jx; ++f; }
     if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
+}
+
+// Receivers at node x of a row whose CSR entries are [rb, re): record the
+// fields of the pre-collision state g.
+template <typename T, int Q>
+__device__ inline void record_node(const Receivers &rc, int rb, int re, int x, const T (&g)[Q], T c2) {
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += g[i];
+        jx += T(cxv<Q>(i)) * g[i];
+        jy += T(cyv<Q>(i)) * g[i];
+    }
+    int lo = rb, hi = re;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (rc.xs[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    for (; lo < re && rc.xs[lo] == x; ++lo)
+        write_fields<T>(rc, rc.slot[lo], rho, jx, jy, c2);
+}
+
+// Post-collision state of node (x, y): collision, source w_i S at the source
+// node, sponge (evaluated at column xsp).
+template <typename T, int Q, int KIND>
+__device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int xsp, int y, double s_n,
+                                 T (&out)[Q]) {
+    T gs[Q], w[Q];
+    collide<T, Q, KIND>(g, c2, p.coll, gs, w);
+    if (y == p.src_y && x == p.src_x) {
+        const T sn = T(s_n);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+    }
+    const T sf = sponge_factor<T>(xsp, y, p.nx, p.ny, p.sponge_width, p.sponge_smax);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
 }
 
 // ---- refinement interface (D2Q5, factor 2) -------------------------------------
@@ -275,7 +338,7 @@ __device__ inline void rescale_collide_store_impl(const InterfaceParams &p, type
     rescale_collide<S, KIND>(p, gh, x, y, out);
     S *dst = reinterpret_cast<S *>(p.dst);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) dst[i * p.dst_pstride + k] = S(out[i]);
+    for (int i = 0; i < 5; ++i) dst[i * p.dst_pstride + k] = to_store<S>(out[i]);
 }
 
 // Interpolation stencil of fine outer-ring node (i, j): coincident nodes
@@ -470,26 +533,11 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
     S outv[Q][V];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        T gj[Q], gs[Q], w[Q];
+        T gj[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
         const int x = x0 + j;
-        if (rb < re && x < nx) {
-            T rho = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                rho += gj[i];
-                jx += T(cxv<Q>(i)) * gj[i];
-                jy += T(cyv<Q>(i)) * gj[i];
-            }
-            int lo = rb, hi = re;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
-            }
-            for (; lo < re && p.rec.xs[lo] == x; ++lo)
-                write_fields<T>(p.rec, p.rec.slot[lo], rho, jx, jy, c2v[j]);
-        }
+        if (rb < re && x < nx) record_node<T, Q>(p.rec, rb, re, x, gj, c2v[j]);
         if ((p.partial || p.rho_out) && x < nx) {
             T rho = T(0);
 #pragma unroll
@@ -497,15 +545,10 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
             local += double(rho);
             if (p.rho_out) reinterpret_cast<T *>(p.rho_out)[(int64_t)y * nx + x] = rho;
         }
-        collide<T, Q, KIND>(gj, c2v[j], p.coll, gs, w);
-        if (y == p.src_y && x == p.src_x) {
-            const T sn = T(p.s_n);
+        T po[Q];
+        post_node<T, Q, KIND>(p, gj, c2v[j], x, min(x, nx - 1), y, p.s_n, po);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
-        }
-        const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) outv[i][j] = S(gs[i] * sf);
+        for (int i = 0; i < Q; ++i) outv[i][j] = to_store<S>(po[i]);
         if constexpr (Q == 5) {
             if (p.restrict_on && x < nx && !((x | y) & 1)) {
                 // this fine node coincides with a coarse node: on the coarse
@@ -523,7 +566,7 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
                 const int r = y == 0 ? x : y == ny - 1 ? nx + x : x == 0 ? 2 * nx + y - 1 : 2 * nx + ny - 2 + y - 1;
                 const T *rb = reinterpret_cast<const T *>(p.ring_buf);
 #pragma unroll
-                for (int i = 0; i < 5; ++i) outv[i][j] = S(rb[i * p.ring_n + r]);
+                for (int i = 0; i < 5; ++i) outv[i][j] = to_store<S>(rb[i * p.ring_n + r]);
             }
         }
     }
@@ -733,6 +776,233 @@ __global__ __launch_bounds__(kBlock) void k_misfit(const T *traces, const T *obs
 // parity live in device memory, so the same launch sequence can be captured
 // once and replayed.  The per-node update is update_tile(), identical to the
 // single-grid step, so a shot's results do not depend on its batch mates.
+// ---- two time steps per launch ------------------------------------------------
+// Temporal blocking: one pass reads h(n) and writes h(n+2), so every
+// population element crosses HBM once per two updates.  A wavefront owns a
+// strip of columns and a segment of kT2Rows rows: it loads the segment's rows
+// of h(n) plus two halo rows on each side, all at once (of the outermost halo
+// rows only the population that streams into the segment), then walks down
+// the rows computing h(n+1) (from the rows above, at and below, in
+// registers) and h(n+2), storing each finished row.  Pulls along x come from
+// the neighbouring lane (cross-lane shuffle).  The strip carries kT2Halo halo
+// lanes on each side (two columns are needed), chosen so that strip edges
+// fall on 64-byte boundaries: measured on MI355X, strips whose edges split
+// 32/64-byte words, and waves that stream one row at a time, reach only
+// 3-4.5 TB/s, while all-rows-at-once loads with aligned edges match a
+// row-major pass (5.5-5.8 TB/s).  Halo rows and lanes are computed
+// redundantly and never stored; the halo's h(n+1) is the same arithmetic at
+// the same node (rounded to the storage format), so the result equals two
+// launches of the one-step kernel bit for bit.  Only rows and columns the
+// wave owns are recorded.
+constexpr int kT2Block = 256;
+constexpr int kT2Halo = 4;    // halo lanes per side
+
+// Rows per segment: all segment rows plus four halo rows sit in registers,
+// so the larger states (D2Q9, FP64, FP16 storage with 4 columns per lane)
+// take shorter segments.
+template <typename S, int Q>
+constexpr int t2_rows() { return (Q == 5 && sizeof(S) == 4) ? 8 : 4; }
+
+template <typename S> struct Tb {
+    static constexpr int V = sizeof(S) == 8 ? 1 : int(8 / sizeof(S));   // 8-byte lane accesses
+    static constexpr int H = kT2Halo;
+    static constexpr int OW = (64 - 2 * H) * V;                          // owned columns per wave (448 B)
+};
+
+template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_vector_type(V), aligned(sizeof(S)))); };
+
+// One row (all populations) of the lane's V columns, converted to T.  VEC:
+// one vector access at the lane's wrapped first column xv (the lane's
+// columns are contiguous after the wrap when nx is a multiple of V);
+// otherwise element accesses at the wrapped columns xw.
+template <bool VEC, int SEL, typename S, typename T, int Q, int V>
+__device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, int64_t rowoff, int xv,
+                                 const int (&xw)[V], T (&out)[Q][V]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if ((SEL > 0 && cyv<Q>(i) <= 0) || (SEL < 0 && cyv<Q>(i) >= 0)) {   // not needed from this row
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(0);
+            continue;
+        }
+        const S *r = base + i * pstride + rowoff;
+        if constexpr (VEC && V > 1) {
+            typedef typename LaneVec<V, S>::type vt;
+            vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(r + xv));
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(t[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(__builtin_nontemporal_load(r + xw[j]));
+        }
+    }
+}
+
+template <bool VEC, typename T, int V>
+__device__ inline void load_c2row(const T *__restrict__ c2, int64_t rowoff, int xv, const int (&xw)[V], T (&out)[V]) {
+    if constexpr (VEC && V > 1) {
+        typedef typename LaneVec<V, T>::type vt;
+        vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(c2 + rowoff + xv));
+#pragma unroll
+        for (int j = 0; j < V; ++j) out[j] = t[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) out[j] = __builtin_nontemporal_load(c2 + rowoff + xw[j]);
+    }
+}
+
+// Pulled (pre-collision) state of one row from the rows above (U, y - 1),
+// at (C) and below (D, y + 1) it: g_i(x) = h_i(x - c_i).
+template <typename T, int Q, int V>
+__device__ inline void pull_row2(const T (&U)[Q][V], const T (&C)[Q][V], const T (&D)[Q][V], T (&g)[Q][V]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T r[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) r[j] = cyv<Q>(i) > 0 ? U[i][j] : cyv<Q>(i) < 0 ? D[i][j] : C[i][j];
+        if (cxv<Q>(i) > 0) {          // from x - 1
+            const T l = __shfl_up(r[V - 1], 1, 64);
+#pragma unroll
+            for (int j = V - 1; j > 0; --j) g[i][j] = r[j - 1];
+            g[i][0] = l;
+        } else if (cxv<Q>(i) < 0) {   // from x + 1
+            const T rr = __shfl_down(r[0], 1, 64);
+#pragma unroll
+            for (int j = 0; j < V - 1; ++j) g[i][j] = r[j + 1];
+            g[i][V - 1] = rr;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) g[i][j] = r[j];
+        }
+    }
+}
+
+template <typename S, int Q, int KIND, bool VEC>
+__global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
+    using T = typename Tr<S>::T;
+    constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = t2_rows<S, Q>(), K = LY + 4;
+    const int nx = p.nx, ny = p.ny;
+    const int nstrip = (nx + OW - 1) / OW;
+    const int nseg = (ny + LY - 1) / LY;
+    // wave-uniform (so that the row and loop arithmetic is scalar)
+    const int wave = blockIdx.x * (kT2Block / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
+    const int lane = threadIdx.x & 63;
+    const int sx = wave % nstrip, sy = wave / nstrip;
+    const int xl = sx * OW - H * V + lane * V;   // first column of this lane
+    const int y0 = sy * LY, y1 = min(y0 + LY, ny);
+    int xw[V];
+    bool own[V];
+    const bool own_lane = lane >= H && lane < 64 - H;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        xw[j] = wrapi(xl + j, nx);
+        own[j] = own_lane && xl + j < nx;
+    }
+    const int xv = xw[0];   // VEC: the lane's columns are xv .. xv + V - 1
+    const S *src = reinterpret_cast<const S *>(p.src);
+    S *dst = reinterpret_cast<S *>(p.dst);
+    const T *c2 = reinterpret_cast<const T *>(p.c2);
+    Receivers rec2 = p.rec;
+    rec2.col = p.rec.col + 1;
+
+    // all rows of h(n) at once: R[k] is row y0 - 2 + k (wrapped)
+    T R[K][Q][V], C[K][V];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t ro = (int64_t)wrapi(y0 - 2 + k, ny) * nx;
+        if (k == 0) {
+            load_row2<VEC, 1, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+        } else if (k == K - 1) {
+            load_row2<VEC, -1, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+        } else {
+            load_row2<VEC, 0, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+            load_c2row<VEC, T, V>(c2, ro, xv, xw, C[k]);
+        }
+    }
+    // this segment's slice of the receiver row table, in LDS (a vector-memory
+    // load of it would make the arithmetic below wait for every row load)
+    __shared__ int32_t s_rows[kT2Block / 64][LY + 1];
+    int32_t *rows = s_rows[wave - blockIdx.x * (kT2Block / 64)];
+    const bool has_rec = p.rec.row_ptr != nullptr;
+    if (has_rec) {
+        if (lane <= y1 - y0) rows[lane] = p.rec.row_ptr[y0 + lane];
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    T H1[K][Q][V];   // h(n+1) rows 1 .. K-2 (same indexing as R)
+#pragma unroll
+    for (int k = 2; k < K; ++k) {
+        {
+            // h(n+1) at row m = k - 1 from h(n) rows m-1, m, m+1
+            const int m = k - 1;
+            const int gm = y0 - 2 + m;   // unwrapped row
+            const int wm = wrapi(gm, ny);
+            T g[Q][V];
+            pull_row2<T, Q, V>(R[m - 1], R[m], R[m + 1], g);
+            int rb = 0, re = 0;
+            if (has_rec && gm >= y0 && gm < y1) {
+                rb = rows[gm - y0];
+                re = rows[gm - y0 + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                T gj[Q], po[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+                if (rb < re && own[j]) record_node<T, Q>(p.rec, rb, re, xw[j], gj, C[m][j]);
+                post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], xw[j], wm, p.s_n, po);
+                // rounded to the storage format, as a stored h(n+1) would be
+#pragma unroll
+                for (int i = 0; i < Q; ++i) H1[m][i][j] = T(to_store<S>(po[i]));
+            }
+        }
+        if (k >= 4) {
+            // h(n+2) at row mm = k - 2 from h(n+1) rows mm-1, mm, mm+1
+            const int mm = k - 2;
+            const int gm = y0 - 2 + mm;   // in [y0, y0 + LY)
+            if (gm < y1) {
+                T g[Q][V];
+                pull_row2<T, Q, V>(H1[mm - 1], H1[mm], H1[mm + 1], g);
+                int rb = 0, re = 0;
+                if (has_rec) {
+                    rb = rows[gm - y0];
+                    re = rows[gm - y0 + 1];
+                }
+                S outv[Q][V];
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    T gj[Q], po[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+                    if (rb < re && own[j]) record_node<T, Q>(rec2, rb, re, xw[j], gj, C[mm][j]);
+                    post_node<T, Q, KIND>(p, gj, C[mm][j], xw[j], xw[j], gm, p.s_n2, po);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) outv[i][j] = to_store<S>(po[i]);
+                }
+                const int64_t ro = (int64_t)gm * nx;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    S *r = dst + i * p.pstride + ro;
+                    if constexpr (VEC && V > 1) {
+                        if (own[0]) {   // nx is a multiple of V: an owned lane owns all its columns
+                            typedef typename LaneVec<V, S>::type vt;
+                            vt t;
+#pragma unroll
+                            for (int j = 0; j < V; ++j) t[j] = outv[i][j];
+                            __builtin_nontemporal_store(t, reinterpret_cast<vt *>(r + xv));
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < V; ++j)
+                            if (own[j]) __builtin_nontemporal_store(outv[i][j], r + xw[j]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename S, int Q, int KIND>
 __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
     constexpr int V = Tr<S>::V;
@@ -815,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(S *pop, int64_t pstride,
     for (int i = 0; i < Q; ++i) {
         T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
         T cj = T(cxv<Q>(i)) * x + T(cyv<Q>(i)) * y;
-        pop[i * pstride + k] = S(w[i] * r + (i == 0 ? T(0) : kj * cj));
+        pop[i * pstride + k] = to_store<S>(w[i] * r + (i == 0 ? T(0) : kj * cj));
     }
 }
 
@@ -962,6 +1232,46 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull, hipStream_t 
     case ST_F16: return step_dispatch<_Float16>(p, pull, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename S>
+static hipError_t step2_dispatch(const StepParams &p, hipStream_t s) {
+    constexpr int OW = Tb<S>::OW;
+    const int ly = p.q == 5 ? t2_rows<S, 5>() : t2_rows<S, 9>();
+    const int64_t waves = (int64_t)((p.nx + OW - 1) / OW) * ((p.ny + ly - 1) / ly);
+    dim3 grid((unsigned)((waves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const int kind = p.coll.kind;
+    // vector accesses need every lane's columns contiguous after the wrap
+    const bool vec = p.nx % Tb<S>::V == 0;
+#define LBW_L2(QQ, KK)                                                                        \
+    do {                                                                                      \
+        if (vec) hipLaunchKernelGGL((k_step2<S, QQ, KK, true>), grid, dim3(kT2Block), 0, s, p);  \
+        else hipLaunchKernelGGL((k_step2<S, QQ, KK, false>), grid, dim3(kT2Block), 0, s, p);     \
+    } while (0)
+    if (p.q == 5) { if (kind == 0) LBW_L2(5, 0); else LBW_L2(5, 1); }
+    else if constexpr (sizeof(S) != 2) { if (kind == 0) LBW_L2(9, 0); else LBW_L2(9, 1); }
+    else return hipErrorInvalidValue;   // not offered: see step2_supported
+#undef LBW_L2
+    return hipGetLastError();
+}
+
+hipError_t launch_step2(int storage, const StepParams &p, hipStream_t s) {
+    if (p.nx < 1 || p.ny < 1) return hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: return step2_dispatch<float>(p, s);
+    case ST_F64: return step2_dispatch<double>(p, s);
+    case ST_F16: return step2_dispatch<_Float16>(p, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int step2_owned_columns(int storage) {
+    return storage == ST_F32 ? Tb<float>::OW : storage == ST_F64 ? Tb<double>::OW : Tb<_Float16>::OW;
+}
+
+bool step2_supported(int storage, int q) {
+    // FP16 storage with D2Q9 would hold its 4-column lanes' rows in scratch
+    return !(storage == ST_F16 && q == 9);
 }
 
 int step_vwidth(int storage) {

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -65,6 +66,7 @@ int validate(const lb_grid_desc *d) {
     if (d->ckpt_every < 0 || d->ckpt_capacity < 0) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
+    if (d->steps_per_launch < 0 || d->steps_per_launch > 1) return LB_E_RANGE;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -743,6 +745,35 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
     return LB_OK;
 }
 
+// Whether the next two steps can go into one launch.
+bool two_step_ok(const lb_grid *h) {
+    if (h->d.steps_per_launch == 1 || h->patch || h->sum_rho) return false;
+    if (!lbw::step2_supported(h->storage, h->q)) return false;
+    if (h->ckpt_valid && (h->t + 2) % h->d.ckpt_every == 0) return false;   // h(t+1) must exist
+    return true;
+}
+
+// Steps t -> t+2 in one launch (columns t+1 and t+2).
+int two_steps(lb_grid *h) {
+    const int64_t col = h->t + 1;
+    if (h->ckpt_valid && col % h->d.ckpt_every == 0) {
+        int rc = save_checkpoint(h, col, false);
+        if (rc) return rc;
+    }
+    Lattice &g = h->main;
+    StepParams p = base_params(h, g, true);
+    p.src = g.curp();
+    p.dst = g.prevp();
+    p.s_n = source_at(h, col);
+    p.s_n2 = source_at(h, col + 1);
+    if (recording(h)) attach_receivers(h, g, p, col);
+    LB_TRY(h, lbw::launch_step2(h->storage, p, h->stream));
+    g.cur = 1 - g.cur;
+    g.prev_pre = 0;
+    h->t = col + 1;
+    return LB_OK;
+}
+
 int lb_step_n(lb_grid *h, int64_t n) {
     if (!h) return LB_E_INVALID;
     if (h->sticky) return h->sticky;
@@ -752,8 +783,18 @@ int lb_step_n(lb_grid *h, int64_t n) {
     if (h->d.ckpt_every > 0 && (h->t + n) / h->d.ckpt_every >= h->d.ckpt_capacity) return LB_E_RANGE;
     int rc;
     if (!h->collided && (rc = initial_collision(h))) return rc;
-    for (int64_t k = 0; k < n; ++k)
-        if ((rc = one_step(h))) return rc;
+    // the last launch of a call is a one-step launch: the fields (and the
+    // saved state) of time t are read from h(t-1), which a two-step launch
+    // does not store
+    for (int64_t k = 0; k < n;) {
+        if (n - k >= 3 && two_step_ok(h)) {
+            if ((rc = two_steps(h))) return rc;
+            k += 2;
+        } else {
+            if ((rc = one_step(h))) return rc;
+            k += 1;
+        }
+    }
     return LB_OK;
 }
 

@@ -48,7 +48,7 @@ def run_oracle(case):
     return out
 
 
-def make_grid(case, precision):
+def make_grid(case, precision, steps_per_launch=0):
     from paper_1704_03172_amd import lbwave
     kw = scheme_kwargs(case)
     rec = case.get("receivers")
@@ -62,14 +62,16 @@ def make_grid(case, precision):
                        sponge_width=case.get("sponge_width", 0),
                        sponge_sigma_max=case.get("sponge_sigma_max", 0.0),
                        trace_capacity=case["nsteps"] + 1, max_receivers=max(nrec, 1),
-                       **extra)
+                       steps_per_launch=steps_per_launch, **extra)
 
 
-def run_gpu(case, precision="f32", chunks=None, on_device=False):
+def run_gpu(case, precision="f32", chunks=None, on_device=False, sum_rho=True, steps_per_launch=0):
     """Run the case through the C-ABI.  chunks: list of step counts whose sum
-    is nsteps (exercises repeated lb_step_n calls)."""
+    is nsteps (exercises repeated lb_step_n calls).  Recording the sum of rho
+    keeps lb_step_n at one step per launch; sum_rho=False lets it take two
+    steps per launch (unless steps_per_launch=1)."""
     import torch
-    grid = make_grid(case, precision)
+    grid = make_grid(case, precision, steps_per_launch)
     ny, nx = case["ny"], case["nx"]
     c2 = case["c2"]
     rho0 = case.get("rho0", np.zeros((ny, nx)))
@@ -86,7 +88,7 @@ def run_gpu(case, precision="f32", chunks=None, on_device=False):
     traces = None
     if case.get("receivers") is not None:
         traces = grid.record(case["receivers"], fields=FIELDS)
-    sums = None if "patch" in case else grid.record_sum_rho()
+    sums = None if ("patch" in case or not sum_rho) else grid.record_sum_rho()
     for n in (chunks or [case["nsteps"]]):
         grid.step(n)
     grid.sync()

@@ -52,7 +52,7 @@ def test_desc_layout_matches_c(lw):
     assert d.tau == 0.5 and list(d.s) == [1, 1, 1, 2, 2, 2, 1, 1, 2]
     assert d.d2q9_ratio == 0.25 and d.sponge_width == 0 and d.sponge_sigma_max == 0.0
     assert (d.patch_enable, d.patch_refine, d.patch_overlap_out, d.patch_overlap_in) == (0, 2, 2, 2)
-    assert d.trace_capacity == 0 and d.max_receivers == 0
+    assert d.trace_capacity == 0 and d.max_receivers == 0 and d.steps_per_launch == 0
     assert ctypes.sizeof(lw.Desc) == 184
 
 
@@ -76,6 +76,8 @@ def test_desc_layout_matches_c(lw):
     (dict(nx=256, ny=256, patch=(2, 96, 64, 64)), -2),
     (dict(nx=256, ny=256, patch=(96, 96, 64, 64), sponge_width=100), -2),
     (dict(nx=256, ny=256, patch=(96, 96, 4, 64)), -2),
+    (dict(steps_per_launch=1), 0),
+    (dict(steps_per_launch=2), -2),
 ])
 def test_validate(lw, kw, code):
     args = dict(nx=64, ny=64)

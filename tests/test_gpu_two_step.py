@@ -1,0 +1,122 @@
+"""Two time steps per launch (temporal blocking) on the GPU.
+
+lb_step_n takes two steps per launch unless the sum of rho is recorded, a
+patch is present, a checkpoint falls between the two steps or the descriptor
+asks for one step per launch.  The two-step kernel must give the same bits
+as two launches of the one-step kernel: the tests below compare the two
+paths bitwise over lattices, collisions, storage formats, grid shapes that
+leave ragged wavefront strips and segments, segment heights, odd step counts
+and chunked calls, with receivers on strip and segment boundaries and on the
+periodic seam, and hold the two-step path to the FP64 oracle bars.
+"""
+import numpy as np
+import pytest
+
+from paper_1704_03172_amd import inputs
+from tests.harness import FIELDS, run_gpu, run_oracle
+from tests.test_gpu_parity import compare, layered_case
+
+pytestmark = pytest.mark.gpu
+
+
+def same(a, b):
+    assert a["time"] == b["time"]
+    np.testing.assert_array_equal(a["traces"], b["traces"])
+    for f in FIELDS:
+        np.testing.assert_array_equal(a["fields"][f], b["fields"][f])
+
+
+def both(case, precision, **kw):
+    one = run_gpu(case, precision, sum_rho=False, steps_per_launch=1)
+    two = run_gpu(case, precision, sum_rho=False, **kw)
+    assert np.abs(one["traces"]).max() > 0
+    same(one, two)
+    return two
+
+
+def boundary_receivers(nx, ny):
+    """Receivers on the strip edges of every storage format (owned widths
+    112 for FP32, 56 for FP64, 224 for FP16 storage), on 8-row segment edges
+    and on the periodic seam."""
+    xs = {0, 1, nx - 1, nx - 2}
+    for w in (56, 112, 224):
+        for k in range(1, nx // w + 1):
+            xs.update({k * w - 1, k * w, k * w + 1})
+    ys = {0, 1, ny - 1, ny - 2}
+    for k in range(1, ny // 8 + 1):
+        ys.update({8 * k - 1, 8 * k})
+    xs = sorted(x for x in xs if 0 <= x < nx)
+    ys = sorted(y for y in ys if 0 <= y < ny)
+    return np.array([(x, y) for y in ys for x in xs[::3]] + [(x, ys[len(ys) // 2]) for x in xs],
+                    dtype=np.int32)
+
+
+SCHEMES = [(5, "bgk", None), (5, "mrt", [1, 1, 1, 1.6, 1.3]), (9, "bgk", None),
+           (9, "mrt", [1, 1, 1, 2, 2, 2, 1, 1, 2])]
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("q,collision,s", SCHEMES)
+def test_two_step_equals_one_step(precision, q, collision, s):
+    case = layered_case(700, 45, q=q, collision=collision, s=s, nsteps=61)
+    case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(700, 45)])
+    two = both(case, precision)
+    if precision != "f16s":
+        compare(case, precision, gpu=two)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 2), (5, 7), (56, 61), (112, 16), (113, 17),
+                                   (224, 3), (2, 300), (1029, 3), (448, 9)])
+def test_two_step_shapes(precision, nx, ny):
+    rho, jx, jy = inputs.random_fields(nx, ny, seed=nx * 17 + ny)
+    rng = np.random.default_rng(nx * ny + 3)
+    for q in (5, 9):
+        case = {"nx": nx, "ny": ny, "q": q, "collision": "mrt" if q == 9 else "bgk",
+                "tau": 0.5, "s": [1, 1, 1, 2, 2, 2, 1, 1, 2][:q],
+                "c2": rng.uniform(0.05, 0.45, (ny, nx)), "rho0": rho, "jx0": jx, "jy0": jy,
+                "nsteps": 27, "sponge_width": 1 if min(nx, ny) > 4 else 0, "sponge_sigma_max": 0.1,
+                "source": (nx - 1, 0), "wavelet": 1e-3 * inputs.ricker_wavelet(28, 0.1),
+                "receivers": np.concatenate([np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2)],
+                                                      dtype=np.int32), boundary_receivers(nx, ny)])}
+        two = both(case, precision)
+        compare(case, precision, gpu=two)
+
+
+@pytest.mark.parametrize("ny", [8, 9, 15, 16, 17, 23, 40])
+def test_segment_edges(ny):
+    """Grid heights around multiples of the 8-row segment (ragged last
+    segment, a single segment, rows that wrap into the next segment), D2Q9
+    MRT so that every direction crosses the segment edges."""
+    case = layered_case(300, ny, q=9, collision="mrt", s=[1, 1, 1, 2, 2, 2, 1, 1, 2], nsteps=40,
+                        sponge=2)
+    case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
+    two = both(case, "f32")
+    compare(case, "f32", gpu=two)
+
+
+def test_chunked_calls_mix_one_and_two_step_launches():
+    case = layered_case(500, 40, nsteps=75)
+    one = run_gpu(case, "f32", sum_rho=False, steps_per_launch=1)
+    two = run_gpu(case, "f32", sum_rho=False, chunks=[1, 2, 3, 0, 5, 29, 35])
+    same(one, two)
+
+
+def test_sum_rho_recording_keeps_one_step_and_matches():
+    """With the sum of rho recorded every step lb_step_n takes one step per
+    launch; traces and fields equal those of the two-step path."""
+    case = layered_case(400, 36, nsteps=50)
+    a = run_gpu(case, "f32", sum_rho=True)
+    b = run_gpu(case, "f32", sum_rho=False)
+    same(a, b)
+
+
+def test_two_step_vs_oracle_pulse_f64():
+    """The 128^2 periodic Gaussian-pulse case (tau = 1, FP64) through the
+    two-step path: rho field against the oracle at the FP64 bar."""
+    wl = inputs.pulse_workload()
+    case = {"nx": 128, "ny": 128, "q": 5, "collision": "bgk", "tau": 1.0,
+            "c2": wl["c2"], "rho0": wl["rho0"], "nsteps": wl["nsteps"],
+            "receivers": np.array([(64, 64), (0, 0), (127, 127), (70, 64)], dtype=np.int32)}
+    ref = run_oracle(case)
+    compare(case, "f64", gpu=run_gpu(case, "f64", sum_rho=False), ref=ref)
