@@ -159,6 +159,15 @@ __device__ inline void weights(T c2, const Collision &c, T (&w)[Q]) {
     }
 }
 
+// c_i . J with the lattice velocity's components (0, +-1) resolved at compile
+// time (no multiplications by 0 or 1).
+template <typename T, int Q>
+__device__ inline T cdot(int i, T jx, T jy) {
+    const int cx = cxv<Q>(i), cy = cyv<Q>(i);
+    const T ax = cx > 0 ? jx : -jx, ay = cy > 0 ? jy : -jy;
+    return cx != 0 ? (cy != 0 ? ax + ay : ax) : (cy != 0 ? ay : T(0));
+}
+
 // Collision of one node: out = g - C (g - g^eq) with the linear equilibrium
 // g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I, MRT
 // C = M^-1 S M applied through the non-conserved moments only.
@@ -178,7 +187,7 @@ __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&ou
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
-        T cj = T(cxv<Q>(i)) * jx + T(cyv<Q>(i)) * jy;
+        T cj = cdot<T, Q>(i, jx, jy);
         T geq = fmaT(w[i], rho, i == 0 ? T(0) : kj * cj);
         d[i] = g[i] - geq;
     }
@@ -211,13 +220,19 @@ __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&ou
     }
 }
 
+// Sponge factor of a node at distance d (in nodes) from the nearest edge.
 template <typename T>
-__device__ inline T sponge_factor(int x, int y, int nx, int ny, int L, double smax) {
-    if (L <= 0) return T(1);
-    int d = min(min(x, y), min(nx - 1 - x, ny - 1 - y));
-    if (d >= L) return T(1);
+__device__ inline T sponge_at(int d, int L, double smax) {
+    if (L <= 0 || d >= L) return T(1);
     T f = T(L - d) / T(L);
     return T(1) - T(smax) * f * f;
+}
+
+__device__ inline int edge_dist(int x, int y, int nx, int ny) { return min(min(x, y), min(nx - 1 - x, ny - 1 - y)); }
+
+template <typename T>
+__device__ inline T sponge_factor(int x, int y, int nx, int ny, int L, double smax) {
+    return sponge_at<T>(edge_dist(x, y, nx, ny), L, smax);
 }
 
 template <typename T>
@@ -253,9 +268,9 @@ __device__ inline void record_node(const Receivers &rc, int rb, int re, int x, c
 }
 
 // Post-collision state of node (x, y): collision, source w_i S at the source
-// node, sponge (evaluated at column xsp).
+// node, sponge (dedge: the node's distance to the nearest grid edge).
 template <typename T, int Q, int KIND>
-__device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int xsp, int y, double s_n,
+__device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int y, int dedge, double s_n,
                                  T (&out)[Q]) {
     T gs[Q], w[Q];
     collide<T, Q, KIND>(g, c2, p.coll, gs, w);
@@ -264,7 +279,7 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
 #pragma unroll
         for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
     }
-    const T sf = sponge_factor<T>(xsp, y, p.nx, p.ny, p.sponge_width, p.sponge_smax);
+    const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
 }
@@ -546,7 +561,7 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
             if (p.rho_out) reinterpret_cast<T *>(p.rho_out)[(int64_t)y * nx + x] = rho;
         }
         T po[Q];
-        post_node<T, Q, KIND>(p, gj, c2v[j], x, min(x, nx - 1), y, p.s_n, po);
+        post_node<T, Q, KIND>(p, gj, c2v[j], x, y, edge_dist(min(x, nx - 1), y, nx, ny), p.s_n, po);
 #pragma unroll
         for (int i = 0; i < Q; ++i) outv[i][j] = to_store<S>(po[i]);
         if constexpr (Q == 5) {
@@ -786,10 +801,10 @@ __global__ __launch_bounds__(kBlock) void k_misfit(const T *traces, const T *obs
 // registers) and h(n+2), storing each finished row.  Pulls along x come from
 // the neighbouring lane (cross-lane shuffle).  The strip carries kT2Halo halo
 // lanes on each side (two columns are needed), chosen so that strip edges
-// fall on 64-byte boundaries: measured on MI355X, strips whose edges split
-// 32/64-byte words, and waves that stream one row at a time, reach only
-// 3-4.5 TB/s, while all-rows-at-once loads with aligned edges match a
-// row-major pass (5.5-5.8 TB/s).  Halo rows and lanes are computed
+// fall on 64-byte boundaries: measured on MI355X with copy kernels of this
+// access pattern, strips whose edges split 32/64-byte words, and waves that
+// stream one row at a time, reach only 3-4.5 TB/s, while all-rows-at-once
+// loads with aligned edges match a row-major pass (5.5-5.8 TB/s).  Halo rows and lanes are computed
 // redundantly and never stored; the halo's h(n+1) is the same arithmetic at
 // the same node (rounded to the storage format), so the result equals two
 // launches of the one-step kernel bit for bit.  Only rows and columns the
@@ -815,7 +830,12 @@ template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_
 // one vector access at the lane's wrapped first column xv (the lane's
 // columns are contiguous after the wrap when nx is a multiple of V);
 // otherwise element accesses at the wrapped columns xw.
-template <bool VEC, int SEL, typename S, typename T, int Q, int V>
+template <typename U>
+__device__ inline U ld_hint(const U *p, bool keep) {
+    return keep ? *p : __builtin_nontemporal_load(p);
+}
+
+template <bool VEC, int SEL, bool KEEP, typename S, typename T, int Q, int V>
 __device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, int64_t rowoff, int xv,
                                  const int (&xw)[V], T (&out)[Q][V]) {
 #pragma unroll
@@ -828,28 +848,49 @@ __device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, in
         const S *r = base + i * pstride + rowoff;
         if constexpr (VEC && V > 1) {
             typedef typename LaneVec<V, S>::type vt;
-            vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(r + xv));
+            vt t = ld_hint(reinterpret_cast<const vt *>(r + xv), KEEP);
 #pragma unroll
             for (int j = 0; j < V; ++j) out[i][j] = T(t[j]);
         } else {
 #pragma unroll
-            for (int j = 0; j < V; ++j) out[i][j] = T(__builtin_nontemporal_load(r + xw[j]));
+            for (int j = 0; j < V; ++j) out[i][j] = T(ld_hint(r + xw[j], KEEP));
         }
     }
 }
 
-template <bool VEC, typename T, int V>
+template <bool VEC, bool KEEP, typename T, int V>
 __device__ inline void load_c2row(const T *__restrict__ c2, int64_t rowoff, int xv, const int (&xw)[V], T (&out)[V]) {
     if constexpr (VEC && V > 1) {
         typedef typename LaneVec<V, T>::type vt;
-        vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(c2 + rowoff + xv));
+        vt t = ld_hint(reinterpret_cast<const vt *>(c2 + rowoff + xv), KEEP);
 #pragma unroll
         for (int j = 0; j < V; ++j) out[j] = t[j];
     } else {
 #pragma unroll
-        for (int j = 0; j < V; ++j) out[j] = __builtin_nontemporal_load(c2 + rowoff + xw[j]);
+        for (int j = 0; j < V; ++j) out[j] = ld_hint(c2 + rowoff + xw[j], KEEP);
     }
 }
+
+// Whole-wave lane shifts by one lane (DPP wave_shr:1 / wave_shl:1, GFX9
+// encodings 0x138 / 0x130): from_lower(v) in lane l is v of lane l - 1,
+// from_upper(v) is v of lane l + 1 (the end lanes keep their own value;
+// they are halo lanes).
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename T>
+__device__ inline T dpp_shift(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+template <typename T> __device__ inline T from_lower(T v) { return dpp_shift<0x138>(v); }
+template <typename T> __device__ inline T from_upper(T v) { return dpp_shift<0x130>(v); }
 
 // Pulled (pre-collision) state of one row from the rows above (U, y - 1),
 // at (C) and below (D, y + 1) it: g_i(x) = h_i(x - c_i).
@@ -861,12 +902,12 @@ __device__ inline void pull_row2(const T (&U)[Q][V], const T (&C)[Q][V], const T
 #pragma unroll
         for (int j = 0; j < V; ++j) r[j] = cyv<Q>(i) > 0 ? U[i][j] : cyv<Q>(i) < 0 ? D[i][j] : C[i][j];
         if (cxv<Q>(i) > 0) {          // from x - 1
-            const T l = __shfl_up(r[V - 1], 1, 64);
+            const T l = from_lower(r[V - 1]);
 #pragma unroll
             for (int j = V - 1; j > 0; --j) g[i][j] = r[j - 1];
             g[i][0] = l;
         } else if (cxv<Q>(i) < 0) {   // from x + 1
-            const T rr = __shfl_down(r[0], 1, 64);
+            const T rr = from_upper(r[0]);
 #pragma unroll
             for (int j = 0; j < V - 1; ++j) g[i][j] = r[j + 1];
             g[i][V - 1] = rr;
@@ -884,8 +925,16 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
     const int nx = p.nx, ny = p.ny;
     const int nstrip = (nx + OW - 1) / OW;
     const int nseg = (ny + LY - 1) / LY;
+    // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8);
+    // renumber them so that each XCD gets a contiguous range of strips and
+    // segments, whose shared halo rows then meet in that XCD's L2.
+    int blk = blockIdx.x;
+    {
+        const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blk % 8;
+        blk = x8 * q8 + min(x8, r8) + blk / 8;
+    }
     // wave-uniform (so that the row and loop arithmetic is scalar)
-    const int wave = blockIdx.x * (kT2Block / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = blk * (kT2Block / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
     const int lane = threadIdx.x & 63;
     const int sx = wave % nstrip, sy = wave / nstrip;
@@ -900,30 +949,40 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
         own[j] = own_lane && xl + j < nx;
     }
     const int xv = xw[0];   // VEC: the lane's columns are xv .. xv + V - 1
+    int dxw[V];             // distance of each column to the nearest side edge
+#pragma unroll
+    for (int j = 0; j < V; ++j) dxw[j] = min(xw[j], nx - 1 - xw[j]);
     const S *src = reinterpret_cast<const S *>(p.src);
     S *dst = reinterpret_cast<S *>(p.dst);
     const T *c2 = reinterpret_cast<const T *>(p.c2);
     Receivers rec2 = p.rec;
     rec2.col = p.rec.col + 1;
 
-    // all rows of h(n) at once: R[k] is row y0 - 2 + k (wrapped)
+    // all rows of h(n) at once: R[k] is row y0 - 2 + k (wrapped).  Rows that
+    // the neighbouring segments also read (the two halo rows and the two edge
+    // rows on each side) are loaded with the ordinary cache policy, so that
+    // the segment loaded second finds them in L2; the others stream
+    // (nontemporal).
     T R[K][Q][V], C[K][V];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t ro = (int64_t)wrapi(y0 - 2 + k, ny) * nx;
         if (k == 0) {
-            load_row2<VEC, 1, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+            load_row2<VEC, 1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
         } else if (k == K - 1) {
-            load_row2<VEC, -1, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+            load_row2<VEC, -1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+        } else if (k < 4 || k >= K - 4) {
+            load_row2<VEC, 0, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+            load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
         } else {
-            load_row2<VEC, 0, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
-            load_c2row<VEC, T, V>(c2, ro, xv, xw, C[k]);
+            load_row2<VEC, 0, false, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
+            load_c2row<VEC, false, T, V>(c2, ro, xv, xw, C[k]);
         }
     }
     // this segment's slice of the receiver row table, in LDS (a vector-memory
     // load of it would make the arithmetic below wait for every row load)
     __shared__ int32_t s_rows[kT2Block / 64][LY + 1];
-    int32_t *rows = s_rows[wave - blockIdx.x * (kT2Block / 64)];
+    int32_t *rows = s_rows[wave - blk * (kT2Block / 64)];
     const bool has_rec = p.rec.row_ptr != nullptr;
     if (has_rec) {
         if (lane <= y1 - y0) rows[lane] = p.rec.row_ptr[y0 + lane];
@@ -951,7 +1010,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
                 if (rb < re && own[j]) record_node<T, Q>(p.rec, rb, re, xw[j], gj, C[m][j]);
-                post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], xw[j], wm, p.s_n, po);
+                post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), p.s_n, po);
                 // rounded to the storage format, as a stored h(n+1) would be
 #pragma unroll
                 for (int i = 0; i < Q; ++i) H1[m][i][j] = T(to_store<S>(po[i]));
@@ -976,7 +1035,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
 #pragma unroll
                     for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
                     if (rb < re && own[j]) record_node<T, Q>(rec2, rb, re, xw[j], gj, C[mm][j]);
-                    post_node<T, Q, KIND>(p, gj, C[mm][j], xw[j], xw[j], gm, p.s_n2, po);
+                    post_node<T, Q, KIND>(p, gj, C[mm][j], xw[j], gm, min(dxw[j], min(gm, ny - 1 - gm)), p.s_n2, po);
 #pragma unroll
                     for (int i = 0; i < Q; ++i) outv[i][j] = to_store<S>(po[i]);
                 }
