@@ -1,8 +1,10 @@
 // lb_batch.cpp -- batched executor behind the lb_batch_* calls of
 // include/lbwave.h: many independent shots of the linear LB scheme advance
-// together in one launch per step, with per-shot time and buffer parity kept
-// on the device so that a tick of k steps is captured once as a HIP graph
-// and replayed until the set of active shots changes.
+// together, two steps per launch (the temporally blocked kernel; one step
+// for the configuration it does not serve, and for the odd step of a tick),
+// with per-shot time and buffer parity kept on the device so that a tick of
+// k steps is captured once as a HIP graph and replayed until the set of
+// active shots changes.
 #include "lbwave.h"
 #include "lb_host.h"
 #include "lb_internal.h"
@@ -22,7 +24,7 @@ using lbw::ShotEntry;
 using lbw::ShotState;
 
 struct BatchLayout {
-    size_t table = 0, state = 0, prefix = 0, order = 0, scratch = 0, total = 0;
+    size_t table = 0, state = 0, prefix = 0, wprefix = 0, order = 0, scratch = 0, total = 0;
 };
 
 BatchLayout batch_layout(int32_t max_shots) {
@@ -32,6 +34,7 @@ BatchLayout batch_layout(int32_t max_shots) {
     L.table = take((size_t)max_shots * sizeof(ShotEntry));
     L.state = take((size_t)max_shots * sizeof(ShotState));
     L.prefix = take(((size_t)max_shots + 1) * sizeof(int64_t));
+    L.wprefix = take(((size_t)max_shots + 1) * sizeof(int64_t));
     L.order = take((size_t)max_shots * sizeof(int32_t));
     L.scratch = take(256);
     L.total = off;
@@ -56,13 +59,15 @@ struct lb_batch {
     ShotEntry *d_table = nullptr;
     ShotState *d_state = nullptr;
     int64_t *d_prefix = nullptr;
+    int64_t *d_wprefix = nullptr;
     int32_t *d_order = nullptr;
     int32_t *d_scratch = nullptr;
     std::vector<ShotEntry> table;
     std::vector<char> used;
     std::vector<int32_t> order;
-    std::vector<int64_t> prefix;
-    int64_t total_blocks = 0;
+    std::vector<int64_t> prefix, wprefix;
+    int64_t total_blocks = 0, total_waves = 0;
+    bool two = false;                  // two steps per launch
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -115,16 +120,21 @@ ShotLayout shot_layout(const lb_batch *b, const lb_shot_desc *s) {
 int rebuild(lb_batch *b) {
     b->order.clear();
     b->prefix.assign(1, 0);
+    b->wprefix.assign(1, 0);
     for (int32_t k = 0; k < b->max_shots; ++k) {
         if (!b->used[(size_t)k]) continue;
         const ShotEntry &e = b->table[(size_t)k];
         b->order.push_back(k);
         b->prefix.push_back(b->prefix.back() + (int64_t)e.bx * e.ny);
+        b->wprefix.push_back(b->wprefix.back() + lbw::step2_waves(b->storage, b->q, e.nx, e.ny));
     }
     b->total_blocks = b->prefix.back();
+    b->total_waves = b->wprefix.back();
     if (!b->order.empty()) {
         BT_TRY(b, hipMemcpyAsync(b->d_order, b->order.data(), b->order.size() * 4, hipMemcpyHostToDevice, b->stream));
         BT_TRY(b, hipMemcpyAsync(b->d_prefix, b->prefix.data(), b->prefix.size() * 8, hipMemcpyHostToDevice,
+                                 b->stream));
+        BT_TRY(b, hipMemcpyAsync(b->d_wprefix, b->wprefix.data(), b->wprefix.size() * 8, hipMemcpyHostToDevice,
                                  b->stream));
     }
     BT_TRY(b, hipStreamSynchronize(b->stream));
@@ -137,15 +147,26 @@ BatchParams params(const lb_batch *b) {
     p.table = b->d_table;
     p.state = b->d_state;
     p.prefix = b->d_prefix;
+    p.wprefix = b->d_wprefix;
     p.order = b->d_order;
     p.nact = (int32_t)b->order.size();
     p.coll = b->coll;
     return p;
 }
 
+// k steps of every active shot (a shot stops at its last step): k / 2
+// two-step launches and, for odd k, one one-step launch.
 int enqueue_steps(lb_batch *b, int64_t k) {
     BatchParams p = params(b);
-    for (int64_t i = 0; i < k; ++i) {
+    int64_t one = k;
+    if (b->two) {
+        for (int64_t i = 0; i < k / 2; ++i) {
+            BT_TRY(b, lbw::launch_step2_batch(b->storage, b->q, p, b->total_waves, b->stream));
+            BT_TRY(b, lbw::launch_batch_advance2(b->d_state, b->d_order, p.nact, b->stream));
+        }
+        one = k % 2;
+    }
+    for (int64_t i = 0; i < one; ++i) {
         BT_TRY(b, lbw::launch_step_batch(b->storage, b->q, p, b->total_blocks, b->stream));
         BT_TRY(b, lbw::launch_batch_advance(b->d_state, b->d_order, p.nact, b->stream));
     }
@@ -207,10 +228,12 @@ int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots, void *d_works
     b->stream = (hipStream_t)stream;
     b->use_graph = use_graph ? 1 : 0;
     b->max_shots = max_shots;
+    b->two = lbw::step2_supported(b->storage, b->q) && scheme->steps_per_launch != 1;
     char *ws = (char *)d_workspace;
     b->d_table = (ShotEntry *)(ws + L.table);
     b->d_state = (ShotState *)(ws + L.state);
     b->d_prefix = (int64_t *)(ws + L.prefix);
+    b->d_wprefix = (int64_t *)(ws + L.wprefix);
     b->d_order = (int32_t *)(ws + L.order);
     b->d_scratch = (int32_t *)(ws + L.scratch);
     b->table.assign((size_t)max_shots, ShotEntry());

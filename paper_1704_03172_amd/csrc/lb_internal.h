@@ -171,6 +171,7 @@ struct BatchParams {
     const ShotEntry *table = nullptr;        // [max_shots]
     ShotState *state = nullptr;              // [max_shots]
     const int64_t *prefix = nullptr;         // [nact + 1] first block of each active shot
+    const int64_t *wprefix = nullptr;        // [nact + 1] first two-step wave of each active shot
     const int32_t *order = nullptr;          // [nact] slot of each active shot
     int32_t nact = 0;
     Collision coll;
@@ -184,6 +185,11 @@ int step_vwidth(int storage);
 int step_tile_nodes(int storage);   // x-nodes covered by one step block
 hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s);
 hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact, hipStream_t s);
+// Two-step batch launch (step2_supported configurations): every active shot
+// advances two steps, or one if one is left; then launch_batch_advance2.
+int64_t step2_waves(int storage, int q, int32_t nx, int32_t ny);
+hipError_t launch_step2_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s);
+hipError_t launch_batch_advance2(ShotState *state, const int32_t *order, int nact, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
 // Two pull steps in one launch: reads h(n) from p.src, writes h(n+2) to

@@ -918,23 +918,23 @@ __device__ inline void pull_row2(const T (&U)[Q][V], const T (&C)[Q][V], const T
     }
 }
 
+// Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8);
+// renumbered, each XCD takes a contiguous range of strips and segments, whose
+// shared halo rows then meet in that XCD's L2.
+__device__ inline int xcd_block() {
+    const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, b = blockIdx.x, x8 = b % 8;
+    return x8 * q8 + min(x8, r8) + b / 8;
+}
+
+// Wave `wave` (of nstrip * nseg for this grid) of a two-step launch; wib: the
+// wave's index in its block.  single: take one step only (h(n+1) is stored).
 template <typename S, int Q, int KIND, bool VEC>
-__global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
+__device__ inline void step2_wave(const StepParams &p, int wave, int wib, bool single) {
     using T = typename Tr<S>::T;
     constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = t2_rows<S, Q>(), K = LY + 4;
     const int nx = p.nx, ny = p.ny;
     const int nstrip = (nx + OW - 1) / OW;
     const int nseg = (ny + LY - 1) / LY;
-    // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8);
-    // renumber them so that each XCD gets a contiguous range of strips and
-    // segments, whose shared halo rows then meet in that XCD's L2.
-    int blk = blockIdx.x;
-    {
-        const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blk % 8;
-        blk = x8 * q8 + min(x8, r8) + blk / 8;
-    }
-    // wave-uniform (so that the row and loop arithmetic is scalar)
-    const int wave = blk * (kT2Block / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
     const int lane = threadIdx.x & 63;
     const int sx = wave % nstrip, sy = wave / nstrip;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
     // this segment's slice of the receiver row table, in LDS (a vector-memory
     // load of it would make the arithmetic below wait for every row load)
     __shared__ int32_t s_rows[kT2Block / 64][LY + 1];
-    int32_t *rows = s_rows[wave - blk * (kT2Block / 64)];
+    int32_t *rows = s_rows[wib];
     const bool has_rec = p.rec.row_ptr != nullptr;
     if (has_rec) {
         if (lane <= y1 - y0) rows[lane] = p.rec.row_ptr[y0 + lane];
@@ -1015,8 +1015,18 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) H1[m][i][j] = T(to_store<S>(po[i]));
             }
+            if (single && gm >= y0 && gm < y1) {   // one step: h(n+1) is the result
+                const int64_t ro = (int64_t)gm * nx;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    S *r = dst + i * p.pstride + ro;
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        if (own[j]) __builtin_nontemporal_store(S(H1[m][i][j]), r + xw[j]);
+                }
+            }
         }
-        if (k >= 4) {
+        if (k >= 4 && !single) {
             // h(n+2) at row mm = k - 2 from h(n+1) rows mm-1, mm, mm+1
             const int mm = k - 2;
             const int gm = y0 - 2 + mm;   // in [y0, y0 + LY)
@@ -1062,6 +1072,13 @@ __global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
     }
 }
 
+template <typename S, int Q, int KIND, bool VEC>
+__global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
+    // wave-uniform (so that the row and loop arithmetic is scalar)
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    step2_wave<S, Q, KIND, VEC>(p, xcd_block() * (kT2Block / 64) + wib, wib, false);
+}
+
 template <typename S, int Q, int KIND>
 __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
     constexpr int V = Tr<S>::V;
@@ -1101,6 +1118,59 @@ __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
 
 // After a batched step: every active, unfinished shot moves to the next time
 // and swaps its buffers.
+// Two steps (one for a shot with one step left) of every active shot in one
+// launch: wave w belongs to the active shot a with wprefix[a] <= w <
+// wprefix[a+1] (waves of nstrip x nseg per shot).
+template <typename S, int Q, int KIND>
+__global__ __launch_bounds__(kT2Block) void k_step2_batch(BatchParams bp) {
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
+    if (w >= bp.wprefix[bp.nact]) return;
+    int lo = 0, hi = bp.nact - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bp.wprefix[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int slot = bp.order[lo];
+    const ShotState ss = bp.state[slot];
+    if (!ss.active || ss.t >= ss.t_end) return;
+    const ShotEntry &e = bp.table[slot];
+    StepParams p;
+    p.src = ss.cur ? e.pop1 : e.pop0;
+    p.dst = ss.cur ? e.pop0 : e.pop1;
+    p.c2 = e.c2;
+    p.nx = e.nx;
+    p.ny = e.ny;
+    p.pstride = e.pstride;
+    p.q = Q;
+    p.coll = bp.coll;
+    p.sponge_width = e.sponge_width;
+    p.sponge_smax = e.sponge_smax;
+    p.src_x = e.src_x;
+    p.src_y = e.src_y;
+    const int64_t tn = ss.t + 1;
+    p.s_n = tn < e.wavelet_len ? e.wavelet[tn] : 0.0;
+    p.s_n2 = tn + 1 < e.wavelet_len ? e.wavelet[tn + 1] : 0.0;
+    p.rec = e.rec;
+    p.rec.col = tn;
+    const bool single = ss.t_end - ss.t == 1;
+    const int lw = int(w - bp.wprefix[lo]);
+    if (e.nx % Tb<S>::V == 0) step2_wave<S, Q, KIND, true>(p, lw, wib, single);
+    else step2_wave<S, Q, KIND, false>(p, lw, wib, single);
+}
+
+// After a two-step batch launch: each active shot advanced by min(2, steps
+// left) in one buffer swap.
+__global__ __launch_bounds__(kBlock) void k_batch_advance2(ShotState *state, const int32_t *order, int nact) {
+    int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nact) return;
+    ShotState &ss = state[order[a]];
+    if (ss.active && ss.t < ss.t_end) {
+        ss.t += min<int64_t>(2, ss.t_end - ss.t);
+        ss.cur ^= 1;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_batch_advance(ShotState *state, const int32_t *order, int nact) {
     int a = blockIdx.x * kBlock + threadIdx.x;
     if (a >= nact) return;
@@ -1352,6 +1422,38 @@ hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t 
     else if (storage == ST_F64) { if (q == 5) LBW_B(double, 5); else LBW_B(double, 9); }
     else { if (q == 5) LBW_B(_Float16, 5); else LBW_B(_Float16, 9); }
 #undef LBW_B
+    return hipGetLastError();
+}
+
+int64_t step2_waves(int storage, int q, int32_t nx, int32_t ny) {
+    const int ow = step2_owned_columns(storage);
+    int ly;
+    if (storage == ST_F32) ly = q == 5 ? t2_rows<float, 5>() : t2_rows<float, 9>();
+    else if (storage == ST_F64) ly = q == 5 ? t2_rows<double, 5>() : t2_rows<double, 9>();
+    else ly = q == 5 ? t2_rows<_Float16, 5>() : t2_rows<_Float16, 9>();
+    return (int64_t)((nx + ow - 1) / ow) * ((ny + ly - 1) / ly);
+}
+
+hipError_t launch_step2_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s) {
+    if (nwaves <= 0 || bp.nact <= 0) return hipSuccess;
+    if (!step2_supported(storage, q)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const bool mrt = bp.coll.kind == 1;
+#define LBW_B2(SS, QQ)                                                                             \
+    do {                                                                                           \
+        if (mrt) hipLaunchKernelGGL((k_step2_batch<SS, QQ, 1>), grid, dim3(kT2Block), 0, s, bp);   \
+        else hipLaunchKernelGGL((k_step2_batch<SS, QQ, 0>), grid, dim3(kT2Block), 0, s, bp);       \
+    } while (0)
+    if (storage == ST_F32) { if (q == 5) LBW_B2(float, 5); else LBW_B2(float, 9); }
+    else if (storage == ST_F64) { if (q == 5) LBW_B2(double, 5); else LBW_B2(double, 9); }
+    else LBW_B2(_Float16, 5);
+#undef LBW_B2
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance2(ShotState *state, const int32_t *order, int nact, hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_advance2, dim3(blocks_for(nact)), dim3(kBlock), 0, s, state, order, nact);
     return hipGetLastError();
 }
 

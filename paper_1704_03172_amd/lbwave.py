@@ -370,19 +370,20 @@ def shot_desc(nx, ny, src, nsteps, nrec, sponge_width=0, sponge_sigma_max=0.0):
 
 
 class Batch:
-    """Batched executor: many shots advance together in one launch per step,
-    captured as a HIP graph per tick (lb_batch_* calls).
+    """Batched executor: many shots advance together, two steps per launch
+    (steps_per_launch=1: one), captured as a HIP graph per tick (lb_batch_*
+    calls).
 
     Runs on its own (default-priority) stream so that ticks can be captured.
     """
 
     def __init__(self, max_shots, lattice=5, collision="bgk", precision="f32", tau=0.5,
-                 s=None, ratio=0.25, use_graph=True, device=None):
+                 s=None, ratio=0.25, use_graph=True, device=None, steps_per_launch=0):
         import torch
         self._torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.scheme = make_desc(1, 1, lattice=lattice, collision=collision, precision=precision,
-                                tau=tau, s=s, ratio=ratio)
+                                tau=tau, s=s, ratio=ratio, steps_per_launch=steps_per_launch)
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.max_shots = int(max_shots)
         self.stream = torch.cuda.Stream(self.device)

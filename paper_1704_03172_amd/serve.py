@@ -55,7 +55,7 @@ class ShotServer:
 
     def __init__(self, budget_bytes=64 << 30, max_slots=32, tick_steps=None,
                  precision="f32", use_graph=True, keep_traces=False, batch=None,
-                 policy="sjf", node_cap=4096 * 4096, tick_ms=20.0, rate_lups=1.3e11):
+                 policy="sjf", node_cap=4096 * 4096, tick_ms=20.0, rate_lups=2.0e11):
         import torch
         from . import lbwave
         self.torch = torch

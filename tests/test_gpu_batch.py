@@ -25,12 +25,12 @@ def shot(nx, ny, nsteps, seed, nrec=16):
 SHOTS = [shot(300, 200, 150, 1), shot(1100, 64, 90, 2), shot(64, 64, 200, 3), shot(2049, 33, 160, 4)]
 
 
-def run_batch(schedule, tick, use_graph=True, max_shots=4):
+def run_batch(schedule, tick, use_graph=True, max_shots=4, steps_per_launch=0):
     """schedule: list of (tick_index, shot) admissions.  Returns traces per
     schedule entry (numpy), after every shot finished."""
     from paper_1704_03172_amd import lbwave
     import torch
-    b = lbwave.Batch(max_shots, use_graph=use_graph)
+    b = lbwave.Batch(max_shots, use_graph=use_graph, steps_per_launch=steps_per_launch)
     out = {}
     slots = {}
     pending = list(enumerate(schedule))
@@ -71,6 +71,19 @@ def test_graph_replays_match_eager_launches():
     e = run_batch(sched, tick=9, use_graph=False)
     for i in range(3):
         np.testing.assert_array_equal(g[i], e[i])
+
+
+@pytest.mark.parametrize("tick", [7, 16, 33])
+def test_two_step_batch_equals_one_step_batch(tick):
+    """Two steps per batched launch (odd ticks end with a one-step launch;
+    shots with an odd number of steps end with a single step inside a
+    two-step launch) give the bits of one step per launch."""
+    sched = [(0, SHOTS[0]), (1, SHOTS[3]), (2, SHOTS[1]), (2, SHOTS[2]), (0, shot(130, 70, 151, 5))]
+    a = run_batch(sched, tick=tick, steps_per_launch=1, max_shots=5)
+    b = run_batch(sched, tick=tick, max_shots=5)
+    for i in range(5):
+        assert np.abs(a[i]).max() > 0
+        np.testing.assert_array_equal(a[i], b[i])
 
 
 def test_batch_equals_single_grid_path():
