@@ -176,16 +176,28 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
             "misfit": float(phi.item()), "gradient_finite": finite}
 
 
-def measured_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or None when
-    the kernel source changed after the counters were taken."""
+KERNEL_SOURCES = ("lb_step2.hip", "lb_node.h", "lb_internal.h")
+
+
+def kernel_source_sha256():
+    """SHA-256 of the sources that define the two-step kernel, concatenated
+    in KERNEL_SOURCES order."""
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1704_03172_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per two-step launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or
+    None when the kernel sources changed after the counters were taken."""
     prof = os.path.join(ROOT, "profiles", "k_step2_d2q5_bgk_f32_layered4096_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_1704_03172_amd", "csrc", "lb_kernels.hip")
     try:
         text = open(prof).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha256()
     except OSError:
         return None
     fields = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and l[:1].isalpha())

@@ -19,270 +19,22 @@
 // and c^2 traffic is single-use, so loads and stores carry the nontemporal
 // hint (measured on MI355X: +8-11 % HBM throughput over cached accesses for
 // this 11-stream pattern, and +7 % for a plain copy).
+//
+// This one-step kernel serves single steps (the last of a call, sum-of-rho
+// recording, checkpoint boundaries), the refinement patch, whose interface
+// work is fused into it, and the adjoint's forward recompute; runs of steps
+// go to the two-step kernel of lb_step2.hip.  Both take their per-node
+// arithmetic from lb_node.h.
 #include "lb_internal.h"
+#include "lb_node.h"
 
 #include <algorithm>
-
-#include <hip/hip_fp16.h>
-
-// No automatic a*b+c contraction in this file: where the compiler forms fused
-// multiply-adds depends on the surrounding code, so the same per-node
-// arithmetic inlined into different kernels (one step per launch, two steps
-// per launch, the batched executor) could round differently.  The fused
-// multiply-adds of the collision are written out (fmaT) instead.
-#pragma clang fp contract(off)
 
 namespace lbw {
 namespace {
 
 constexpr int kBlock = 256;       // set-up, field and interface kernels
 constexpr int kStepBlock = 128;   // fused step (best of a block-size sweep)
-
-// ---- lattice tables (velocity order of Appendix A) -----------------------
-template <int Q>
-__host__ __device__ constexpr int cxv(int i) {
-    return Q == 5 ? (i == 1 ? 1 : i == 3 ? -1 : 0)
-                  : (i == 1 || i == 5 || i == 8 ? 1 : i == 3 || i == 6 || i == 7 ? -1 : 0);
-}
-template <int Q>
-__host__ __device__ constexpr int cyv(int i) {
-    return Q == 5 ? (i == 2 ? 1 : i == 4 ? -1 : 0)
-                  : (i == 2 || i == 5 || i == 6 ? 1 : i == 4 || i == 7 || i == 8 ? -1 : 0);
-}
-
-// Rows of the moment matrix of Appendix A (non-conserved rows only are
-// used: D2Q5 k = 3 (e), 4 (pxx); D2Q9 k = 3 (e), 4 (pxx), 5 (eps),
-// 6 (qx), 7 (qy), 8 (pxy)).
-template <int Q>
-__host__ __device__ constexpr int mrow(int k, int i) {
-    if (Q == 5) {
-        if (k == 3) return i == 0 ? -4 : 1;
-        if (k == 4) return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
-        return 0;
-    }
-    switch (k) {
-    case 3: return i == 0 ? -4 : (i <= 4 ? -1 : 2);
-    case 4: return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
-    case 5: return i == 0 ? 4 : (i <= 4 ? -2 : 1);
-    case 6: return i == 1 ? -2 : i == 3 ? 2 : (i == 5 || i == 8 ? 1 : (i == 6 || i == 7 ? -1 : 0));
-    case 7: return i == 2 ? -2 : i == 4 ? 2 : (i == 5 || i == 6 ? 1 : (i == 7 || i == 8 ? -1 : 0));
-    case 8: return i == 5 || i == 7 ? 1 : (i == 6 || i == 8 ? -1 : 0);
-    default: return 0;
-    }
-}
-
-// ---- storage traits -------------------------------------------------------
-template <typename S> struct Tr;
-template <> struct Tr<float> {
-    using T = float;
-    static constexpr int V = 4;
-    typedef float vec __attribute__((ext_vector_type(4), aligned(4)));
-};
-template <> struct Tr<double> {
-    using T = double;
-    static constexpr int V = 2;
-    typedef double vec __attribute__((ext_vector_type(2), aligned(8)));
-};
-template <> struct Tr<_Float16> {
-    using T = float;
-    static constexpr int V = 8;
-    typedef _Float16 vec __attribute__((ext_vector_type(8), aligned(2)));
-};
-
-// Conversion of a computed value to the storage format.  For FP16 storage
-// the value is first materialised in FP32 (the empty asm is a value barrier):
-// otherwise the compiler may fold the last multiply and the conversion into
-// one mixed-precision FMA (a single rounding) in some kernels and not in
-// others, and a state stored by different kernels would differ in its bits.
-template <typename S, typename T>
-__device__ inline S to_store(T v) {
-    if constexpr (sizeof(S) < sizeof(T)) asm volatile("" : "+v"(v));
-    return S(v);
-}
-
-template <typename T>
-__device__ inline T fmaT(T a, T b, T c) {
-    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
-    else return __builtin_fmaf(a, b, c);
-}
-
-__device__ inline int wrapi(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
-// V consecutive elements starting at x = xs of one row, periodic in x.
-template <typename S, int V>
-__device__ inline void load_x(const S *__restrict__ row, int xs, int nx, S (&v)[V]) {
-    if (V > 1 && xs >= 0 && xs + V <= nx) {
-        typedef typename Tr<S>::vec vt;
-        vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(row + xs));
-#pragma unroll
-        for (int j = 0; j < V; ++j) v[j] = t[j];
-    } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) v[j] = row[wrapi(xs + j, nx)];
-    }
-}
-
-template <typename S, int V>
-__device__ inline void store_x(S *__restrict__ row, int x0, int nx, const S (&v)[V]) {
-    if (V > 1 && x0 + V <= nx) {
-        typedef typename Tr<S>::vec vt;
-        vt t;
-#pragma unroll
-        for (int j = 0; j < V; ++j) t[j] = v[j];
-        __builtin_nontemporal_store(t, reinterpret_cast<vt *>(row + x0));
-    } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-            if (x0 + j < nx) row[x0 + j] = v[j];
-    }
-}
-
-// ---- the per-node update ---------------------------------------------------
-// Lattice weights from c^2 (Sec. II C): D2Q5 w_i = c^2/2 for movers,
-// w0 = 1 - 2 c^2; D2Q9 w1 = c^2 kax, w5 = r w1, w0 = 1 - 4 w1 - 4 w5.
-template <typename T, int Q>
-__device__ inline void weights(T c2, const Collision &c, T (&w)[Q]) {
-    if (Q == 5) {
-        T w1 = T(0.5) * c2;
-        w[0] = T(1) - T(4) * w1;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) w[i] = w1;
-    } else {
-        T w1 = c2 * T(c.kax);
-        T w5 = w1 * T(c.ratio);
-        w[0] = T(1) - T(4) * w1 - T(4) * w5;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) w[i] = i <= 4 ? w1 : w5;
-    }
-}
-
-// c_i . J with the lattice velocity's components (0, +-1) resolved at compile
-// time (no multiplications by 0 or 1).
-template <typename T, int Q>
-__device__ inline T cdot(int i, T jx, T jy) {
-    const int cx = cxv<Q>(i), cy = cyv<Q>(i);
-    const T ax = cx > 0 ? jx : -jx, ay = cy > 0 ? jy : -jy;
-    return cx != 0 ? (cy != 0 ? ax + ay : ax) : (cy != 0 ? ay : T(0));
-}
-
-// Collision of one node: out = g - C (g - g^eq) with the linear equilibrium
-// g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I, MRT
-// C = M^-1 S M applied through the non-conserved moments only.
-template <typename T, int Q, int KIND>
-__device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&out)[Q], T (&w)[Q]) {
-    T rho = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        rho += g[i];
-        if (cxv<Q>(i) > 0) jx += g[i];
-        if (cxv<Q>(i) < 0) jx -= g[i];
-        if (cyv<Q>(i) > 0) jy += g[i];
-        if (cyv<Q>(i) < 0) jy -= g[i];
-    }
-    weights<T, Q>(c2, c, w);
-    T d[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
-        T cj = cdot<T, Q>(i, jx, jy);
-        T geq = fmaT(w[i], rho, i == 0 ? T(0) : kj * cj);
-        d[i] = g[i] - geq;
-    }
-    if (KIND == 0) {
-        const T om = T(c.omega);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) out[i] = fmaT(-om, d[i], g[i]);
-    } else {
-        T r[9];
-#pragma unroll
-        for (int k = 3; k < Q; ++k) {
-            T m = T(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                int a = mrow<Q>(k, i);
-                if (a != 0) m += T(a) * d[i];
-            }
-            r[k] = T(c.srate[k]) * m;
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T acc = T(0);
-#pragma unroll
-            for (int k = 3; k < Q; ++k) {
-                int a = mrow<Q>(k, i);
-                if (a != 0) acc += T(a) * r[k];
-            }
-            out[i] = g[i] - acc;
-        }
-    }
-}
-
-// Sponge factor of a node at distance d (in nodes) from the nearest edge.
-template <typename T>
-__device__ inline T sponge_at(int d, int L, double smax) {
-    if (L <= 0 || d >= L) return T(1);
-    T f = T(L - d) / T(L);
-    return T(1) - T(smax) * f * f;
-}
-
-__device__ inline int edge_dist(int x, int y, int nx, int ny) { return min(min(x, y), min(nx - 1 - x, ny - 1 - y)); }
-
-template <typename T>
-__device__ inline T sponge_factor(int x, int y, int nx, int ny, int L, double smax) {
-    return sponge_at<T>(edge_dist(x, y, nx, ny), L, smax);
-}
-
-template <typename T>
-__device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, T jy, T c2) {
-    T *tr = reinterpret_cast<T *>(rc.traces);
-    int f = 0;
-    const int64_t plane = (int64_t)rc.nslots * rc.cap;
-    const int64_t base = (int64_t)slot * rc.cap + rc.col;
-    if (rc.what & 1u) { tr[f * plane + base] = c2 * rho; ++f; }
-    if (rc.what & 2u) { tr[f * plane + base] = rho; ++f; }
-    if (rc.what & 4u) { tr[f * plane + base] = jx; ++f; }
-    if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
-}
-
-// Receivers at node x of a row whose CSR entries are [rb, re): record the
-// fields of the pre-collision state g.
-template <typename T, int Q>
-__device__ inline void record_node(const Receivers &rc, int rb, int re, int x, const T (&g)[Q], T c2) {
-    T rho = T(0), jx = T(0), jy = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        rho += g[i];
-        jx += T(cxv<Q>(i)) * g[i];
-        jy += T(cyv<Q>(i)) * g[i];
-    }
-    int lo = rb, hi = re;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (rc.xs[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    for (; lo < re && rc.xs[lo] == x; ++lo)
-        write_fields<T>(rc, rc.slot[lo], rho, jx, jy, c2);
-}
-
-// Post-collision state of node (x, y): collision, source w_i S at the source
-// node, sponge (dedge: the node's distance to the nearest grid edge).
-template <typename T, int Q, int KIND>
-__device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int y, int dedge, double s_n,
-                                 T (&out)[Q]) {
-    T gs[Q], w[Q];
-    collide<T, Q, KIND>(g, c2, p.coll, gs, w);
-    if (y == p.src_y && x == p.src_x) {
-        const T sn = T(s_n);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
-    }
-    const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
-}
 
 // ---- refinement interface (D2Q5, factor 2) -------------------------------------
 template <typename S, typename T>
@@ -791,294 +543,6 @@ __global__ __launch_bounds__(kBlock) void k_misfit(const T *traces, const T *obs
 // parity live in device memory, so the same launch sequence can be captured
 // once and replayed.  The per-node update is update_tile(), identical to the
 // single-grid step, so a shot's results do not depend on its batch mates.
-// ---- two time steps per launch ------------------------------------------------
-// Temporal blocking: one pass reads h(n) and writes h(n+2), so every
-// population element crosses HBM once per two updates.  A wavefront owns a
-// strip of columns and a segment of kT2Rows rows: it loads the segment's rows
-// of h(n) plus two halo rows on each side, all at once (of the outermost halo
-// rows only the population that streams into the segment), then walks down
-// the rows computing h(n+1) (from the rows above, at and below, in
-// registers) and h(n+2), storing each finished row.  Pulls along x come from
-// the neighbouring lane (cross-lane shuffle).  The strip carries kT2Halo halo
-// lanes on each side (two columns are needed), chosen so that strip edges
-// fall on 64-byte boundaries: measured on MI355X with copy kernels of this
-// access pattern, strips whose edges split 32/64-byte words, and waves that
-// stream one row at a time, reach only 3-4.5 TB/s, while all-rows-at-once
-// loads with aligned edges match a row-major pass (5.5-5.8 TB/s).  Halo rows and lanes are computed
-// redundantly and never stored; the halo's h(n+1) is the same arithmetic at
-// the same node (rounded to the storage format), so the result equals two
-// launches of the one-step kernel bit for bit.  Only rows and columns the
-// wave owns are recorded.
-constexpr int kT2Block = 256;
-constexpr int kT2Halo = 4;    // halo lanes per side
-
-// Rows per segment: all segment rows plus four halo rows sit in registers,
-// so the larger states (D2Q9, FP64, FP16 storage with 4 columns per lane)
-// take shorter segments.
-template <typename S, int Q>
-constexpr int t2_rows() { return (Q == 5 && sizeof(S) == 4) ? 8 : 4; }
-
-template <typename S> struct Tb {
-    static constexpr int V = sizeof(S) == 8 ? 1 : int(8 / sizeof(S));   // 8-byte lane accesses
-    static constexpr int H = kT2Halo;
-    static constexpr int OW = (64 - 2 * H) * V;                          // owned columns per wave (448 B)
-};
-
-template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_vector_type(V), aligned(sizeof(S)))); };
-
-// One row (all populations) of the lane's V columns, converted to T.  VEC:
-// one vector access at the lane's wrapped first column xv (the lane's
-// columns are contiguous after the wrap when nx is a multiple of V);
-// otherwise element accesses at the wrapped columns xw.
-template <typename U>
-__device__ inline U ld_hint(const U *p, bool keep) {
-    return keep ? *p : __builtin_nontemporal_load(p);
-}
-
-template <bool VEC, int SEL, bool KEEP, typename S, typename T, int Q, int V>
-__device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, int64_t rowoff, int xv,
-                                 const int (&xw)[V], T (&out)[Q][V]) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if ((SEL > 0 && cyv<Q>(i) <= 0) || (SEL < 0 && cyv<Q>(i) >= 0)) {   // not needed from this row
-#pragma unroll
-            for (int j = 0; j < V; ++j) out[i][j] = T(0);
-            continue;
-        }
-        const S *r = base + i * pstride + rowoff;
-        if constexpr (VEC && V > 1) {
-            typedef typename LaneVec<V, S>::type vt;
-            vt t = ld_hint(reinterpret_cast<const vt *>(r + xv), KEEP);
-#pragma unroll
-            for (int j = 0; j < V; ++j) out[i][j] = T(t[j]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) out[i][j] = T(ld_hint(r + xw[j], KEEP));
-        }
-    }
-}
-
-template <bool VEC, bool KEEP, typename T, int V>
-__device__ inline void load_c2row(const T *__restrict__ c2, int64_t rowoff, int xv, const int (&xw)[V], T (&out)[V]) {
-    if constexpr (VEC && V > 1) {
-        typedef typename LaneVec<V, T>::type vt;
-        vt t = ld_hint(reinterpret_cast<const vt *>(c2 + rowoff + xv), KEEP);
-#pragma unroll
-        for (int j = 0; j < V; ++j) out[j] = t[j];
-    } else {
-#pragma unroll
-        for (int j = 0; j < V; ++j) out[j] = ld_hint(c2 + rowoff + xw[j], KEEP);
-    }
-}
-
-// Whole-wave lane shifts by one lane (DPP wave_shr:1 / wave_shl:1, GFX9
-// encodings 0x138 / 0x130): from_lower(v) in lane l is v of lane l - 1,
-// from_upper(v) is v of lane l + 1 (the end lanes keep their own value;
-// they are halo lanes).
-template <int CTRL>
-__device__ inline uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL, typename T>
-__device__ inline T dpp_shift(T v) {
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
-    } else {
-        const uint64_t u = __builtin_bit_cast(uint64_t, v);
-        const uint32_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
-        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
-    }
-}
-template <typename T> __device__ inline T from_lower(T v) { return dpp_shift<0x138>(v); }
-template <typename T> __device__ inline T from_upper(T v) { return dpp_shift<0x130>(v); }
-
-// Pulled (pre-collision) state of one row from the rows above (U, y - 1),
-// at (C) and below (D, y + 1) it: g_i(x) = h_i(x - c_i).
-template <typename T, int Q, int V>
-__device__ inline void pull_row2(const T (&U)[Q][V], const T (&C)[Q][V], const T (&D)[Q][V], T (&g)[Q][V]) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T r[V];
-#pragma unroll
-        for (int j = 0; j < V; ++j) r[j] = cyv<Q>(i) > 0 ? U[i][j] : cyv<Q>(i) < 0 ? D[i][j] : C[i][j];
-        if (cxv<Q>(i) > 0) {          // from x - 1
-            const T l = from_lower(r[V - 1]);
-#pragma unroll
-            for (int j = V - 1; j > 0; --j) g[i][j] = r[j - 1];
-            g[i][0] = l;
-        } else if (cxv<Q>(i) < 0) {   // from x + 1
-            const T rr = from_upper(r[0]);
-#pragma unroll
-            for (int j = 0; j < V - 1; ++j) g[i][j] = r[j + 1];
-            g[i][V - 1] = rr;
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) g[i][j] = r[j];
-        }
-    }
-}
-
-// Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8);
-// renumbered, each XCD takes a contiguous range of strips and segments, whose
-// shared halo rows then meet in that XCD's L2.
-__device__ inline int xcd_block() {
-    const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, b = blockIdx.x, x8 = b % 8;
-    return x8 * q8 + min(x8, r8) + b / 8;
-}
-
-// Wave `wave` (of nstrip * nseg for this grid) of a two-step launch; wib: the
-// wave's index in its block.  single: take one step only (h(n+1) is stored).
-template <typename S, int Q, int KIND, bool VEC>
-__device__ inline void step2_wave(const StepParams &p, int wave, int wib, bool single) {
-    using T = typename Tr<S>::T;
-    constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = t2_rows<S, Q>(), K = LY + 4;
-    const int nx = p.nx, ny = p.ny;
-    const int nstrip = (nx + OW - 1) / OW;
-    const int nseg = (ny + LY - 1) / LY;
-    if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
-    const int lane = threadIdx.x & 63;
-    const int sx = wave % nstrip, sy = wave / nstrip;
-    const int xl = sx * OW - H * V + lane * V;   // first column of this lane
-    const int y0 = sy * LY, y1 = min(y0 + LY, ny);
-    int xw[V];
-    bool own[V];
-    const bool own_lane = lane >= H && lane < 64 - H;
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-        xw[j] = wrapi(xl + j, nx);
-        own[j] = own_lane && xl + j < nx;
-    }
-    const int xv = xw[0];   // VEC: the lane's columns are xv .. xv + V - 1
-    int dxw[V];             // distance of each column to the nearest side edge
-#pragma unroll
-    for (int j = 0; j < V; ++j) dxw[j] = min(xw[j], nx - 1 - xw[j]);
-    const S *src = reinterpret_cast<const S *>(p.src);
-    S *dst = reinterpret_cast<S *>(p.dst);
-    const T *c2 = reinterpret_cast<const T *>(p.c2);
-    Receivers rec2 = p.rec;
-    rec2.col = p.rec.col + 1;
-
-    // all rows of h(n) at once: R[k] is row y0 - 2 + k (wrapped).  Rows that
-    // the neighbouring segments also read (the two halo rows and the two edge
-    // rows on each side) are loaded with the ordinary cache policy, so that
-    // the segment loaded second finds them in L2; the others stream
-    // (nontemporal).
-    T R[K][Q][V], C[K][V];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t ro = (int64_t)wrapi(y0 - 2 + k, ny) * nx;
-        if (k == 0) {
-            load_row2<VEC, 1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
-        } else if (k == K - 1) {
-            load_row2<VEC, -1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
-        } else if (k < 4 || k >= K - 4) {
-            load_row2<VEC, 0, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
-            load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
-        } else {
-            load_row2<VEC, 0, false, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[k]);
-            load_c2row<VEC, false, T, V>(c2, ro, xv, xw, C[k]);
-        }
-    }
-    // this segment's slice of the receiver row table, in LDS (a vector-memory
-    // load of it would make the arithmetic below wait for every row load)
-    __shared__ int32_t s_rows[kT2Block / 64][LY + 1];
-    int32_t *rows = s_rows[wib];
-    const bool has_rec = p.rec.row_ptr != nullptr;
-    if (has_rec) {
-        if (lane <= y1 - y0) rows[lane] = p.rec.row_ptr[y0 + lane];
-        __builtin_amdgcn_wave_barrier();
-    }
-
-    T H1[K][Q][V];   // h(n+1) rows 1 .. K-2 (same indexing as R)
-#pragma unroll
-    for (int k = 2; k < K; ++k) {
-        {
-            // h(n+1) at row m = k - 1 from h(n) rows m-1, m, m+1
-            const int m = k - 1;
-            const int gm = y0 - 2 + m;   // unwrapped row
-            const int wm = wrapi(gm, ny);
-            T g[Q][V];
-            pull_row2<T, Q, V>(R[m - 1], R[m], R[m + 1], g);
-            int rb = 0, re = 0;
-            if (has_rec && gm >= y0 && gm < y1) {
-                rb = rows[gm - y0];
-                re = rows[gm - y0 + 1];
-            }
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                T gj[Q], po[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
-                if (rb < re && own[j]) record_node<T, Q>(p.rec, rb, re, xw[j], gj, C[m][j]);
-                post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), p.s_n, po);
-                // rounded to the storage format, as a stored h(n+1) would be
-#pragma unroll
-                for (int i = 0; i < Q; ++i) H1[m][i][j] = T(to_store<S>(po[i]));
-            }
-            if (single && gm >= y0 && gm < y1) {   // one step: h(n+1) is the result
-                const int64_t ro = (int64_t)gm * nx;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    S *r = dst + i * p.pstride + ro;
-#pragma unroll
-                    for (int j = 0; j < V; ++j)
-                        if (own[j]) __builtin_nontemporal_store(S(H1[m][i][j]), r + xw[j]);
-                }
-            }
-        }
-        if (k >= 4 && !single) {
-            // h(n+2) at row mm = k - 2 from h(n+1) rows mm-1, mm, mm+1
-            const int mm = k - 2;
-            const int gm = y0 - 2 + mm;   // in [y0, y0 + LY)
-            if (gm < y1) {
-                T g[Q][V];
-                pull_row2<T, Q, V>(H1[mm - 1], H1[mm], H1[mm + 1], g);
-                int rb = 0, re = 0;
-                if (has_rec) {
-                    rb = rows[gm - y0];
-                    re = rows[gm - y0 + 1];
-                }
-                S outv[Q][V];
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    T gj[Q], po[Q];
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
-                    if (rb < re && own[j]) record_node<T, Q>(rec2, rb, re, xw[j], gj, C[mm][j]);
-                    post_node<T, Q, KIND>(p, gj, C[mm][j], xw[j], gm, min(dxw[j], min(gm, ny - 1 - gm)), p.s_n2, po);
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) outv[i][j] = to_store<S>(po[i]);
-                }
-                const int64_t ro = (int64_t)gm * nx;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    S *r = dst + i * p.pstride + ro;
-                    if constexpr (VEC && V > 1) {
-                        if (own[0]) {   // nx is a multiple of V: an owned lane owns all its columns
-                            typedef typename LaneVec<V, S>::type vt;
-                            vt t;
-#pragma unroll
-                            for (int j = 0; j < V; ++j) t[j] = outv[i][j];
-                            __builtin_nontemporal_store(t, reinterpret_cast<vt *>(r + xv));
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < V; ++j)
-                            if (own[j]) __builtin_nontemporal_store(outv[i][j], r + xw[j]);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <typename S, int Q, int KIND, bool VEC>
-__global__ __launch_bounds__(kT2Block) void k_step2(StepParams p) {
-    // wave-uniform (so that the row and loop arithmetic is scalar)
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    step2_wave<S, Q, KIND, VEC>(p, xcd_block() * (kT2Block / 64) + wib, wib, false);
-}
-
 template <typename S, int Q, int KIND>
 __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
     constexpr int V = Tr<S>::V;
@@ -1118,59 +582,6 @@ __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
 
 // After a batched step: every active, unfinished shot moves to the next time
 // and swaps its buffers.
-// Two steps (one for a shot with one step left) of every active shot in one
-// launch: wave w belongs to the active shot a with wprefix[a] <= w <
-// wprefix[a+1] (waves of nstrip x nseg per shot).
-template <typename S, int Q, int KIND>
-__global__ __launch_bounds__(kT2Block) void k_step2_batch(BatchParams bp) {
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
-    if (w >= bp.wprefix[bp.nact]) return;
-    int lo = 0, hi = bp.nact - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (bp.wprefix[mid] <= w) lo = mid; else hi = mid - 1;
-    }
-    const int slot = bp.order[lo];
-    const ShotState ss = bp.state[slot];
-    if (!ss.active || ss.t >= ss.t_end) return;
-    const ShotEntry &e = bp.table[slot];
-    StepParams p;
-    p.src = ss.cur ? e.pop1 : e.pop0;
-    p.dst = ss.cur ? e.pop0 : e.pop1;
-    p.c2 = e.c2;
-    p.nx = e.nx;
-    p.ny = e.ny;
-    p.pstride = e.pstride;
-    p.q = Q;
-    p.coll = bp.coll;
-    p.sponge_width = e.sponge_width;
-    p.sponge_smax = e.sponge_smax;
-    p.src_x = e.src_x;
-    p.src_y = e.src_y;
-    const int64_t tn = ss.t + 1;
-    p.s_n = tn < e.wavelet_len ? e.wavelet[tn] : 0.0;
-    p.s_n2 = tn + 1 < e.wavelet_len ? e.wavelet[tn + 1] : 0.0;
-    p.rec = e.rec;
-    p.rec.col = tn;
-    const bool single = ss.t_end - ss.t == 1;
-    const int lw = int(w - bp.wprefix[lo]);
-    if (e.nx % Tb<S>::V == 0) step2_wave<S, Q, KIND, true>(p, lw, wib, single);
-    else step2_wave<S, Q, KIND, false>(p, lw, wib, single);
-}
-
-// After a two-step batch launch: each active shot advanced by min(2, steps
-// left) in one buffer swap.
-__global__ __launch_bounds__(kBlock) void k_batch_advance2(ShotState *state, const int32_t *order, int nact) {
-    int a = blockIdx.x * kBlock + threadIdx.x;
-    if (a >= nact) return;
-    ShotState &ss = state[order[a]];
-    if (ss.active && ss.t < ss.t_end) {
-        ss.t += min<int64_t>(2, ss.t_end - ss.t);
-        ss.cur ^= 1;
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_batch_advance(ShotState *state, const int32_t *order, int nact) {
     int a = blockIdx.x * kBlock + threadIdx.x;
     if (a >= nact) return;
@@ -1363,46 +774,6 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull, hipStream_t 
     return hipErrorInvalidValue;
 }
 
-template <typename S>
-static hipError_t step2_dispatch(const StepParams &p, hipStream_t s) {
-    constexpr int OW = Tb<S>::OW;
-    const int ly = p.q == 5 ? t2_rows<S, 5>() : t2_rows<S, 9>();
-    const int64_t waves = (int64_t)((p.nx + OW - 1) / OW) * ((p.ny + ly - 1) / ly);
-    dim3 grid((unsigned)((waves + kT2Block / 64 - 1) / (kT2Block / 64)));
-    const int kind = p.coll.kind;
-    // vector accesses need every lane's columns contiguous after the wrap
-    const bool vec = p.nx % Tb<S>::V == 0;
-#define LBW_L2(QQ, KK)                                                                        \
-    do {                                                                                      \
-        if (vec) hipLaunchKernelGGL((k_step2<S, QQ, KK, true>), grid, dim3(kT2Block), 0, s, p);  \
-        else hipLaunchKernelGGL((k_step2<S, QQ, KK, false>), grid, dim3(kT2Block), 0, s, p);     \
-    } while (0)
-    if (p.q == 5) { if (kind == 0) LBW_L2(5, 0); else LBW_L2(5, 1); }
-    else if constexpr (sizeof(S) != 2) { if (kind == 0) LBW_L2(9, 0); else LBW_L2(9, 1); }
-    else return hipErrorInvalidValue;   // not offered: see step2_supported
-#undef LBW_L2
-    return hipGetLastError();
-}
-
-hipError_t launch_step2(int storage, const StepParams &p, hipStream_t s) {
-    if (p.nx < 1 || p.ny < 1) return hipErrorInvalidValue;
-    switch (storage) {
-    case ST_F32: return step2_dispatch<float>(p, s);
-    case ST_F64: return step2_dispatch<double>(p, s);
-    case ST_F16: return step2_dispatch<_Float16>(p, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-int step2_owned_columns(int storage) {
-    return storage == ST_F32 ? Tb<float>::OW : storage == ST_F64 ? Tb<double>::OW : Tb<_Float16>::OW;
-}
-
-bool step2_supported(int storage, int q) {
-    // FP16 storage with D2Q9 would hold its 4-column lanes' rows in scratch
-    return !(storage == ST_F16 && q == 9);
-}
-
 int step_vwidth(int storage) {
     return storage == ST_F32 ? Tr<float>::V : storage == ST_F64 ? Tr<double>::V : Tr<_Float16>::V;
 }
@@ -1422,38 +793,6 @@ hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t 
     else if (storage == ST_F64) { if (q == 5) LBW_B(double, 5); else LBW_B(double, 9); }
     else { if (q == 5) LBW_B(_Float16, 5); else LBW_B(_Float16, 9); }
 #undef LBW_B
-    return hipGetLastError();
-}
-
-int64_t step2_waves(int storage, int q, int32_t nx, int32_t ny) {
-    const int ow = step2_owned_columns(storage);
-    int ly;
-    if (storage == ST_F32) ly = q == 5 ? t2_rows<float, 5>() : t2_rows<float, 9>();
-    else if (storage == ST_F64) ly = q == 5 ? t2_rows<double, 5>() : t2_rows<double, 9>();
-    else ly = q == 5 ? t2_rows<_Float16, 5>() : t2_rows<_Float16, 9>();
-    return (int64_t)((nx + ow - 1) / ow) * ((ny + ly - 1) / ly);
-}
-
-hipError_t launch_step2_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s) {
-    if (nwaves <= 0 || bp.nact <= 0) return hipSuccess;
-    if (!step2_supported(storage, q)) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
-    const bool mrt = bp.coll.kind == 1;
-#define LBW_B2(SS, QQ)                                                                             \
-    do {                                                                                           \
-        if (mrt) hipLaunchKernelGGL((k_step2_batch<SS, QQ, 1>), grid, dim3(kT2Block), 0, s, bp);   \
-        else hipLaunchKernelGGL((k_step2_batch<SS, QQ, 0>), grid, dim3(kT2Block), 0, s, bp);       \
-    } while (0)
-    if (storage == ST_F32) { if (q == 5) LBW_B2(float, 5); else LBW_B2(float, 9); }
-    else if (storage == ST_F64) { if (q == 5) LBW_B2(double, 5); else LBW_B2(double, 9); }
-    else LBW_B2(_Float16, 5);
-#undef LBW_B2
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_advance2(ShotState *state, const int32_t *order, int nact, hipStream_t s) {
-    if (nact <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_advance2, dim3(blocks_for(nact)), dim3(kBlock), 0, s, state, order, nact);
     return hipGetLastError();
 }
 

@@ -1,0 +1,270 @@
+// lb_node.h -- the per-node arithmetic of the linear LB step shared by every
+// step kernel (one step per launch, two steps per launch, the batched
+// executor, the refinement interface): lattice tables, storage traits, the
+// collision, source, sponge and receiver recording of one node.  Device
+// code only; included by the kernel sources (not part of the public
+// interface).
+#pragma once
+
+#include "lb_internal.h"
+
+#include <hip/hip_fp16.h>
+
+// No automatic a*b+c contraction in this file: where the compiler forms fused
+// multiply-adds depends on the surrounding code, so the same per-node
+// arithmetic inlined into different kernels (one step per launch, two steps
+// per launch, the batched executor) could round differently.  The fused
+// multiply-adds of the collision are written out (fmaT) instead.
+#pragma clang fp contract(off)
+
+namespace lbw {
+namespace {
+
+// ---- lattice tables (velocity order of Appendix A) -----------------------
+template <int Q>
+__host__ __device__ constexpr int cxv(int i) {
+    return Q == 5 ? (i == 1 ? 1 : i == 3 ? -1 : 0)
+                  : (i == 1 || i == 5 || i == 8 ? 1 : i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+template <int Q>
+__host__ __device__ constexpr int cyv(int i) {
+    return Q == 5 ? (i == 2 ? 1 : i == 4 ? -1 : 0)
+                  : (i == 2 || i == 5 || i == 6 ? 1 : i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+
+// Rows of the moment matrix of Appendix A (non-conserved rows only are
+// used: D2Q5 k = 3 (e), 4 (pxx); D2Q9 k = 3 (e), 4 (pxx), 5 (eps),
+// 6 (qx), 7 (qy), 8 (pxy)).
+template <int Q>
+__host__ __device__ constexpr int mrow(int k, int i) {
+    if (Q == 5) {
+        if (k == 3) return i == 0 ? -4 : 1;
+        if (k == 4) return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
+        return 0;
+    }
+    switch (k) {
+    case 3: return i == 0 ? -4 : (i <= 4 ? -1 : 2);
+    case 4: return i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0);
+    case 5: return i == 0 ? 4 : (i <= 4 ? -2 : 1);
+    case 6: return i == 1 ? -2 : i == 3 ? 2 : (i == 5 || i == 8 ? 1 : (i == 6 || i == 7 ? -1 : 0));
+    case 7: return i == 2 ? -2 : i == 4 ? 2 : (i == 5 || i == 6 ? 1 : (i == 7 || i == 8 ? -1 : 0));
+    case 8: return i == 5 || i == 7 ? 1 : (i == 6 || i == 8 ? -1 : 0);
+    default: return 0;
+    }
+}
+
+// ---- storage traits -------------------------------------------------------
+template <typename S> struct Tr;
+template <> struct Tr<float> {
+    using T = float;
+    static constexpr int V = 4;
+    typedef float vec __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <> struct Tr<double> {
+    using T = double;
+    static constexpr int V = 2;
+    typedef double vec __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <> struct Tr<_Float16> {
+    using T = float;
+    static constexpr int V = 8;
+    typedef _Float16 vec __attribute__((ext_vector_type(8), aligned(2)));
+};
+
+// Conversion of a computed value to the storage format.  For FP16 storage
+// the value is first materialised in FP32 (the empty asm is a value barrier):
+// otherwise the compiler may fold the last multiply and the conversion into
+// one mixed-precision FMA (a single rounding) in some kernels and not in
+// others, and a state stored by different kernels would differ in its bits.
+template <typename S, typename T>
+__device__ inline S to_store(T v) {
+    if constexpr (sizeof(S) < sizeof(T)) asm volatile("" : "+v"(v));
+    return S(v);
+}
+
+template <typename T>
+__device__ inline T fmaT(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+__device__ inline int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// V consecutive elements starting at x = xs of one row, periodic in x.
+template <typename S, int V>
+__device__ inline void load_x(const S *__restrict__ row, int xs, int nx, S (&v)[V]) {
+    if (V > 1 && xs >= 0 && xs + V <= nx) {
+        typedef typename Tr<S>::vec vt;
+        vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(row + xs));
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = t[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = row[wrapi(xs + j, nx)];
+    }
+}
+
+template <typename S, int V>
+__device__ inline void store_x(S *__restrict__ row, int x0, int nx, const S (&v)[V]) {
+    if (V > 1 && x0 + V <= nx) {
+        typedef typename Tr<S>::vec vt;
+        vt t;
+#pragma unroll
+        for (int j = 0; j < V; ++j) t[j] = v[j];
+        __builtin_nontemporal_store(t, reinterpret_cast<vt *>(row + x0));
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            if (x0 + j < nx) row[x0 + j] = v[j];
+    }
+}
+
+// ---- the per-node update ---------------------------------------------------
+// Lattice weights from c^2 (Sec. II C): D2Q5 w_i = c^2/2 for movers,
+// w0 = 1 - 2 c^2; D2Q9 w1 = c^2 kax, w5 = r w1, w0 = 1 - 4 w1 - 4 w5.
+template <typename T, int Q>
+__device__ inline void weights(T c2, const Collision &c, T (&w)[Q]) {
+    if (Q == 5) {
+        T w1 = T(0.5) * c2;
+        w[0] = T(1) - T(4) * w1;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) w[i] = w1;
+    } else {
+        T w1 = c2 * T(c.kax);
+        T w5 = w1 * T(c.ratio);
+        w[0] = T(1) - T(4) * w1 - T(4) * w5;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) w[i] = i <= 4 ? w1 : w5;
+    }
+}
+
+// c_i . J with the lattice velocity's components (0, +-1) resolved at compile
+// time (no multiplications by 0 or 1).
+template <typename T, int Q>
+__device__ inline T cdot(int i, T jx, T jy) {
+    const int cx = cxv<Q>(i), cy = cyv<Q>(i);
+    const T ax = cx > 0 ? jx : -jx, ay = cy > 0 ? jy : -jy;
+    return cx != 0 ? (cy != 0 ? ax + ay : ax) : (cy != 0 ? ay : T(0));
+}
+
+// Collision of one node: out = g - C (g - g^eq) with the linear equilibrium
+// g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I, MRT
+// C = M^-1 S M applied through the non-conserved moments only.
+template <typename T, int Q, int KIND>
+__device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&out)[Q], T (&w)[Q]) {
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += g[i];
+        if (cxv<Q>(i) > 0) jx += g[i];
+        if (cxv<Q>(i) < 0) jx -= g[i];
+        if (cyv<Q>(i) > 0) jy += g[i];
+        if (cyv<Q>(i) < 0) jy -= g[i];
+    }
+    weights<T, Q>(c2, c, w);
+    T d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
+        T cj = cdot<T, Q>(i, jx, jy);
+        T geq = fmaT(w[i], rho, i == 0 ? T(0) : kj * cj);
+        d[i] = g[i] - geq;
+    }
+    if (KIND == 0) {
+        const T om = T(c.omega);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[i] = fmaT(-om, d[i], g[i]);
+    } else {
+        T r[9];
+#pragma unroll
+        for (int k = 3; k < Q; ++k) {
+            T m = T(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int a = mrow<Q>(k, i);
+                if (a != 0) m += T(a) * d[i];
+            }
+            r[k] = T(c.srate[k]) * m;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 3; k < Q; ++k) {
+                int a = mrow<Q>(k, i);
+                if (a != 0) acc += T(a) * r[k];
+            }
+            out[i] = g[i] - acc;
+        }
+    }
+}
+
+// Sponge factor of a node at distance d (in nodes) from the nearest edge.
+template <typename T>
+__device__ inline T sponge_at(int d, int L, double smax) {
+    if (L <= 0 || d >= L) return T(1);
+    T f = T(L - d) / T(L);
+    return T(1) - T(smax) * f * f;
+}
+
+__device__ inline int edge_dist(int x, int y, int nx, int ny) { return min(min(x, y), min(nx - 1 - x, ny - 1 - y)); }
+
+template <typename T>
+__device__ inline T sponge_factor(int x, int y, int nx, int ny, int L, double smax) {
+    return sponge_at<T>(edge_dist(x, y, nx, ny), L, smax);
+}
+
+template <typename T>
+__device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, T jy, T c2) {
+    T *tr = reinterpret_cast<T *>(rc.traces);
+    int f = 0;
+    const int64_t plane = (int64_t)rc.nslots * rc.cap;
+    const int64_t base = (int64_t)slot * rc.cap + rc.col;
+    if (rc.what & 1u) { tr[f * plane + base] = c2 * rho; ++f; }
+    if (rc.what & 2u) { tr[f * plane + base] = rho; ++f; }
+    if (rc.what & 4u) { tr[f * plane + base] = jx; ++f; }
+    if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
+}
+
+// Receivers at node x of a row whose CSR entries are [rb, re): record the
+// fields of the pre-collision state g.
+template <typename T, int Q>
+__device__ inline void record_node(const Receivers &rc, int rb, int re, int x, const T (&g)[Q], T c2) {
+    T rho = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += g[i];
+        jx += T(cxv<Q>(i)) * g[i];
+        jy += T(cyv<Q>(i)) * g[i];
+    }
+    int lo = rb, hi = re;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (rc.xs[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    for (; lo < re && rc.xs[lo] == x; ++lo)
+        write_fields<T>(rc, rc.slot[lo], rho, jx, jy, c2);
+}
+
+// Post-collision state of node (x, y): collision, source w_i S at the source
+// node, sponge (dedge: the node's distance to the nearest grid edge).
+template <typename T, int Q, int KIND>
+__device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int y, int dedge, double s_n,
+                                 T (&out)[Q]) {
+    T gs[Q], w[Q];
+    collide<T, Q, KIND>(g, c2, p.coll, gs, w);
+    if (y == p.src_y && x == p.src_x) {
+        const T sn = T(s_n);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+    }
+    const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
+}
+
+}  // namespace
+}  // namespace lbw
