@@ -223,10 +223,39 @@ def cpu_baseline(wl, target_s=10.0):
         n += 1
     dt = time.perf_counter() - t0
     nodes = wl["nx"] * wl["ny"]
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": lb_oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model,
             "sample": "%d whole-grid steps of the 4096x4096 layered D2Q5 BGK workload "
                       "(FP64, C loops, OpenMP over rows), %.1f s" % (n, dt)}
+
+
+def pulse_variant(torch, lbwave, inputs):
+    """The 128^2 periodic Gaussian-pulse case (D2Q5 BGK tau = 1, FP64, 500
+    steps, sum of rho recorded every step): launch-bound, so reported in us
+    per step."""
+    wl = inputs.pulse_workload()
+    g = lbwave.Grid(128, 128, lattice=5, collision="bgk", precision="f64", tau=1.0,
+                    trace_capacity=wl["nsteps"] + 1)
+    g.set_medium(wl["c2"])
+    g.set_state(wl["rho0"])
+    g.record_sum_rho()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(wl["nsteps"])
+    e1.record(g.stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    g.close()
+    return {"pulse_D2Q5_BGK_F64_128": {"us_per_step": round(t / wl["nsteps"] * 1e6, 2),
+                                       "steps": wl["nsteps"], "sum_rho_recorded": True}}
 
 
 def main():
@@ -309,6 +338,7 @@ def main():
             del g
             torch.cuda.empty_cache()
         variants.update(refined_variant(torch, lbwave, inputs))
+        variants.update(pulse_variant(torch, lbwave, inputs))
 
     adjoint = None
     if not args.no_adjoint:

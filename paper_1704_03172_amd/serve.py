@@ -93,9 +93,10 @@ class ShotServer:
             return self.k_fixed
         return int(max(10, min(500, self.tick_ms * 1e-3 * self.rate / max(nodes, 1))))
 
-    def run(self, trace):
+    def run(self, trace, progress=False):
         """Serve a list of requests (arrival in seconds from the start);
-        returns (records, summary)."""
+        returns (records, summary).  progress: a line on stderr every 100
+        completed shots."""
         pending = collections.deque(sorted(trace, key=lambda r: r["arrival"]))
         queue = []
         active = {}           # slot -> record
@@ -139,6 +140,8 @@ class ShotServer:
                     used -= rec["bytes"]
                     nodes -= rec["nodes"]
                     done.append(active.pop(slot))
+                    if progress and len(done) % 100 == 0:
+                        print("batched: %d done at %.1f s" % (len(done), now()), file=sys.stderr, flush=True)
         wall = max(r["done"] for r in done) - min(r["arrival"] for r in done) if done else 0.0
         self.traces = traces
         return done, summarize(done, wall)
@@ -147,8 +150,9 @@ class ShotServer:
         self.batch.close()
 
 
-def run_fifo(trace, precision="f32", keep_traces=False):
-    """Baseline: one shot at a time in arrival order, one launch per step."""
+def run_fifo(trace, precision="f32", keep_traces=False, progress=False):
+    """Baseline: one shot at a time in arrival order, through the
+    single-grid lb_step_n path (two steps per launch, no batching)."""
     import torch
     from . import inputs, lbwave
     done = []
@@ -173,6 +177,8 @@ def run_fifo(trace, precision="f32", keep_traces=False):
             traces[req["rid"]] = tr[0].cpu().numpy()
         done.append({"rid": req["rid"], "arrival": req["arrival"], "admit": admit, "done": now(),
                      "n": n, "nsteps": req["nsteps"]})
+        if progress and len(done) % 100 == 0:
+            print("one shot per launch: %d done at %.1f s" % (len(done), now()), file=sys.stderr, flush=True)
         g.close()
         del g, tr
     wall = max(r["done"] for r in done) - min(r["arrival"] for r in done) if done else 0.0
@@ -202,11 +208,11 @@ def main(argv=None):
     if args.mode in ("batch", "both"):
         srv = ShotServer(int(args.budget_gb * (1 << 30)), args.slots, args.tick,
                          policy=args.policy, node_cap=args.node_cap)
-        _, out["batched"] = srv.run(trace)
+        _, out["batched"] = srv.run(trace, progress=True)
         srv.close()
         print("batched", json.dumps(out["batched"]), file=sys.stderr, flush=True)
     if args.mode in ("fifo", "both"):
-        _, out["fifo"] = run_fifo(trace)
+        _, out["fifo"] = run_fifo(trace, progress=True)
         print("fifo", json.dumps(out["fifo"]), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
