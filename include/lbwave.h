@@ -256,8 +256,9 @@ const char *lb_status_string(int code);
 /* ---- batched executor (serving many shots at once) --------------------
  *
  * Many independent shots (grids of different sizes, each with its own medium,
- * source, receivers and step count) advance together: one launch per time
- * step covers the tiles of every active shot, and the shot's time and buffer
+ * source, receivers and step count) advance together: one launch covers two
+ * time steps (the scheme's steps_per_launch = 1: one) of every active shot,
+ * a shot with one step left taking one, and the shot's time and buffer
  * parity live in device memory, so a tick of k steps is captured once as a
  * HIP graph and replayed until the set of shots changes.  Each shot computes
  * exactly what an lb_grid with the same parameters computes (same per-node
@@ -280,8 +281,8 @@ typedef struct {
 size_t lb_batch_workspace_bytes(int32_t max_shots);
 
 /* Create a batch executor.  `scheme` supplies lattice, collision, precision,
- * tau, s and d2q9_ratio (its grid, sponge, patch and capacity fields are
- * ignored; no patch).  use_graph = 1 captures ticks as HIP graphs (needs a
+ * tau, s, d2q9_ratio and steps_per_launch (its grid, sponge, patch and
+ * capacity fields are ignored; no patch).  use_graph = 1 captures ticks as HIP graphs (needs a
  * stream other than the legacy default stream), 0 launches them directly. */
 int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots,
                     void *d_workspace, size_t ws_bytes, void *stream,
