@@ -5,18 +5,18 @@ anomalies, 64-node sponge, Ricker source at >= 20 nodes per wavelength and
 256 surface receivers; D2Q5, BGK tau = 1/2, FP32 populations.  One "step" is
 one time step of the whole grid (pull-stream, moments, per-node weights,
 linear equilibrium, collision, source, sponge, receiver sampling at every
-time).  lb_step_n runs two steps per fused launch (the last launch of a call
-takes one), so the dominant kernel is the two-step kernel: it reads h(n)
-and writes h(n+2), 44 algorithmic bytes per node per launch (24 read, 20
-written), i.e. 22 bytes per lattice update.  Inputs are resident in HBM
-before the timed region.
+time).  lb_step_n runs several steps per fused launch (three for this
+configuration; the last launch of a call takes one), so the dominant kernel
+is the temporally blocked kernel: it reads h(n) and writes h(n+3), 44
+algorithmic bytes per node per launch (24 read, 20 written), i.e. 14.7 bytes
+per lattice update.  Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line: MLUPS (value), roofline of the two-step kernel (its
+Prints ONE JSON line: MLUPS (value), roofline of the blocked kernel (its
 launch duration measured with HIP events as the difference of two runs that
-differ only in the number of two-step launches, against the 8 TB/s HBM
-peak), a measured device-copy bandwidth, comparison variants (MRT, D2Q9,
-FP64, FP16 storage, refinement), the adjoint and serving measurements and
-the CPU oracle timed on a bounded sample.
+differ only in the number of blocked launches, against the 8 TB/s HBM peak),
+a measured device-copy bandwidth, comparison variants (MRT, D2Q9, FP64, FP16
+storage, refinement, the 128^2 pulse), the adjoint and serving measurements
+and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -41,14 +41,26 @@ def bytes_per_lup(q, precision):
     return 2 * q * s + c
 
 
-def launch_counts(nsteps):
-    """(two-step launches, one-step launches) of one lb_step_n(nsteps) call
-    on a grid without patch, sum-of-rho recording or checkpoints: two-step
-    launches while at least three steps remain."""
+def max_steps_per_launch(q, precision):
+    """Steps per launch the blocked kernel offers (as the library decides)."""
+    if q == 5 and precision == "f32":
+        return 3
+    if q == 9 and precision == "f16s":
+        return 1
+    return 2
+
+
+def launch_plan(nsteps, ns_max):
+    """{steps per launch: launches} of one lb_step_n(nsteps) call on a grid
+    without patch, sum-of-rho recording or checkpoints: each launch takes
+    min(ns_max, steps left - 1) steps, the last one a single step."""
+    plan = {}
     k = 0
-    while nsteps - k >= 3:
-        k += 2
-    return k // 2, nsteps - k
+    while k < nsteps:
+        ns = max(1, min(ns_max, nsteps - k - 1))
+        plan[ns] = plan.get(ns, 0) + 1
+        k += ns
+    return plan
 
 
 def log(msg):
@@ -176,11 +188,11 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
             "misfit": float(phi.item()), "gradient_finite": finite}
 
 
-KERNEL_SOURCES = ("lb_step2.hip", "lb_node.h", "lb_internal.h")
+KERNEL_SOURCES = ("lb_blocked.hip", "lb_node.h", "lb_internal.h")
 
 
 def kernel_source_sha256():
-    """SHA-256 of the sources that define the two-step kernel, concatenated
+    """SHA-256 of the sources that define the blocked kernel, concatenated
     in KERNEL_SOURCES order."""
     import hashlib
     h = hashlib.sha256()
@@ -191,10 +203,10 @@ def kernel_source_sha256():
 
 
 def measured_traffic():
-    """HBM bytes per two-step launch from the committed rocprofv3 counter
+    """HBM bytes per blocked launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or
     None when the kernel sources changed after the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "k_step2_d2q5_bgk_f32_layered4096_hbm_counters.md")
+    prof = os.path.join(ROOT, "profiles", "k_stepn3_d2q5_bgk_f32_layered4096_hbm_counters.md")
     try:
         text = open(prof).read()
         sha = kernel_source_sha256()
@@ -297,15 +309,16 @@ def main():
     N = wl["nx"] * wl["ny"]
     cap = steps + warmup + 1
 
-    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + 2 * 401 + 2 * 101)
+    nsl = max_steps_per_launch(5, "f32")
+    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + nsl * 501 + 10)
     log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
     t = time_steps(torch, grid, steps, warmup)
     mlups = N * steps / t / 1e6
-    n2, n1 = launch_counts(steps)
-    # the two-step kernel's launch duration: two calls that differ only in
-    # their number of two-step launches (400 vs 100, one one-step launch each)
-    ta = time_steps(torch, grid, 2 * 400 + 1, 0)
-    tb = time_steps(torch, grid, 2 * 100 + 1, 0)
+    plan = launch_plan(steps, nsl)
+    # the blocked kernel's launch duration: two calls that differ only in
+    # their number of nsl-step launches (400 vs 100, one one-step launch each)
+    ta = time_steps(torch, grid, nsl * 400 + 1, 0)
+    tb = time_steps(torch, grid, nsl * 100 + 1, 0)
     kern_s = (ta - tb) / 300
     bpl = bytes_per_lup(5, "f32")
     achieved = bpl * N / kern_s / 1e9
@@ -326,13 +339,14 @@ def main():
             g = make_layered(lbwave, wl, q, coll, prec, vsteps + 11)
             tv = time_steps(torch, g, vsteps, 10)
             b = bytes_per_lup(q, prec)
-            nb = b * N * sum(launch_counts(vsteps))      # algorithmic bytes of the launches
+            vplan = launch_plan(vsteps, max_steps_per_launch(q, prec))
+            nb = b * N * sum(vplan.values())      # algorithmic bytes of the launches
             variants["D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())] = {
                 "MLUPS": round(N * vsteps / tv / 1e6, 1),
                 "GBs": round(nb / tv / 1e9, 1),
                 "frac_hbm": round(nb / tv / 1e9 / HBM_PEAK_GBS, 4),
                 "bytes_per_node_per_launch": b, "steps": vsteps,
-                "launches_two_step_one_step": list(launch_counts(vsteps))}
+                "launches_by_steps": {str(k): v for k, v in sorted(vplan.items())}}
             log("variant %s %.0f MLUPS" % (list(variants)[-1], N * vsteps / tv / 1e6))
             g.close()
             del g
@@ -380,10 +394,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-                     "kernel": "k_step2<float,5,BGK> (two steps per launch)",
-                     "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": 2 * N,
+                     "kernel": "k_stepn<float,5,BGK,%d> (%d steps per launch)" % (nsl, nsl),
+                     "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": nsl * N,
                      "avg_kernel_us": round(kern_s * 1e6, 3)},
-        "launches_two_step_one_step": [n2, n1],
+        "launches_by_steps": {str(k): v for k, v in sorted(plan.items())},
         "copy_kernel_GBs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "traces_finite": finite,

@@ -107,12 +107,15 @@ typedef struct lb_grid lb_grid;
  *                  workspace grows by ckpt_capacity states, K rho fields and
  *                  two adjoint population sets).  0: no checkpoints.
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
- *   steps_per_launch  0 (default): lb_step_n advances two time steps per
- *                  kernel launch wherever it can (no patch, no sum-rho
- *                  recording, no checkpoint falling between the two; the
- *                  last launch of each call takes one step), which halves
- *                  the HBM traffic per step; the results equal those of one
- *                  step per launch bit for bit.  1: one step per launch.
+ *   steps_per_launch  0 (default): lb_step_n advances several time steps
+ *                  per kernel launch (temporal blocking: three for D2Q5 with
+ *                  FP32 populations, two for the other configurations, one
+ *                  for D2Q9 with FP16 storage) wherever it can (no patch, no
+ *                  sum-rho recording, no checkpoint falling inside a launch;
+ *                  the last launch of each call takes one step), which
+ *                  divides the HBM traffic per step accordingly; the results
+ *                  equal those of one step per launch bit for bit.  1, 2, 3:
+ *                  at most that many steps per launch.
  *   nbatch         independent shots sharing the grid shape (must be 1).
  */
 typedef struct {
@@ -256,9 +259,10 @@ const char *lb_status_string(int code);
 /* ---- batched executor (serving many shots at once) --------------------
  *
  * Many independent shots (grids of different sizes, each with its own medium,
- * source, receivers and step count) advance together: one launch covers two
- * time steps (the scheme's steps_per_launch = 1: one) of every active shot,
- * a shot with one step left taking one, and the shot's time and buffer
+ * source, receivers and step count) advance together: one launch covers up
+ * to three time steps (as the scheme's steps_per_launch allows, see
+ * lb_grid_desc) of every active shot, a shot with fewer steps left taking
+ * those, and the shot's time and buffer
  * parity live in device memory, so a tick of k steps is captured once as a
  * HIP graph and replayed until the set of shots changes.  Each shot computes
  * exactly what an lb_grid with the same parameters computes (same per-node

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbwave.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["lb_kernels.hip", "lb_step2.hip", "lb_runtime.cpp", "lb_batch.cpp"]
+SOURCES = ["lb_kernels.hip", "lb_blocked.hip", "lb_runtime.cpp", "lb_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LBWAVE_ARCH", "gfx950")
 

@@ -1,7 +1,7 @@
 // lb_batch.cpp -- batched executor behind the lb_batch_* calls of
 // include/lbwave.h: many independent shots of the linear LB scheme advance
-// together, two steps per launch (the temporally blocked kernel; one step
-// for the configuration it does not serve, and for the odd step of a tick),
+// together, up to three steps per launch (the temporally blocked kernel;
+// one step per launch for the configuration it does not serve),
 // with per-shot time and buffer parity kept on the device so that a tick of
 // k steps is captured once as a HIP graph and replayed until the set of
 // active shots changes.
@@ -67,7 +67,7 @@ struct lb_batch {
     std::vector<int32_t> order;
     std::vector<int64_t> prefix, wprefix;
     int64_t total_blocks = 0, total_waves = 0;
-    bool two = false;                  // two steps per launch
+    int ns = 1;                        // steps per launch (blocked kernel if > 1)
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -126,16 +126,17 @@ int rebuild(lb_batch *b) {
         const ShotEntry &e = b->table[(size_t)k];
         b->order.push_back(k);
         b->prefix.push_back(b->prefix.back() + (int64_t)e.bx * e.ny);
-        b->wprefix.push_back(b->wprefix.back() + lbw::step2_waves(b->storage, b->q, e.nx, e.ny));
+        if (b->ns > 1) b->wprefix.push_back(b->wprefix.back() + lbw::stepn_waves(b->storage, b->q, b->ns, e.nx, e.ny));
     }
     b->total_blocks = b->prefix.back();
-    b->total_waves = b->wprefix.back();
+    b->total_waves = b->ns > 1 ? b->wprefix.back() : 0;
     if (!b->order.empty()) {
         BT_TRY(b, hipMemcpyAsync(b->d_order, b->order.data(), b->order.size() * 4, hipMemcpyHostToDevice, b->stream));
         BT_TRY(b, hipMemcpyAsync(b->d_prefix, b->prefix.data(), b->prefix.size() * 8, hipMemcpyHostToDevice,
                                  b->stream));
-        BT_TRY(b, hipMemcpyAsync(b->d_wprefix, b->wprefix.data(), b->wprefix.size() * 8, hipMemcpyHostToDevice,
-                                 b->stream));
+        if (b->ns > 1)
+            BT_TRY(b, hipMemcpyAsync(b->d_wprefix, b->wprefix.data(), b->wprefix.size() * 8, hipMemcpyHostToDevice,
+                                     b->stream));
     }
     BT_TRY(b, hipStreamSynchronize(b->stream));
     b->dirty = true;
@@ -154,21 +155,22 @@ BatchParams params(const lb_batch *b) {
     return p;
 }
 
-// k steps of every active shot (a shot stops at its last step): k / 2
-// two-step launches and, for odd k, one one-step launch.
+// k steps of every active shot (a shot stops at its last step): launches of
+// ns steps, the remainder of k in one shorter blocked launch (or, with one
+// step left or no blocked kernel, one-step launches).
 int enqueue_steps(lb_batch *b, int64_t k) {
     BatchParams p = params(b);
-    int64_t one = k;
-    if (b->two) {
-        for (int64_t i = 0; i < k / 2; ++i) {
-            BT_TRY(b, lbw::launch_step2_batch(b->storage, b->q, p, b->total_waves, b->stream));
-            BT_TRY(b, lbw::launch_batch_advance2(b->d_state, b->d_order, p.nact, b->stream));
+    while (k > 0) {
+        const int run = (int)std::min<int64_t>(b->ns, k);
+        if (run > 1) {
+            p.max_run = run;
+            BT_TRY(b, lbw::launch_stepn_batch(b->storage, b->q, b->ns, p, b->total_waves, b->stream));
+            BT_TRY(b, lbw::launch_batch_advance_n(b->d_state, b->d_order, p.nact, run, b->stream));
+        } else {
+            BT_TRY(b, lbw::launch_step_batch(b->storage, b->q, p, b->total_blocks, b->stream));
+            BT_TRY(b, lbw::launch_batch_advance(b->d_state, b->d_order, p.nact, b->stream));
         }
-        one = k % 2;
-    }
-    for (int64_t i = 0; i < one; ++i) {
-        BT_TRY(b, lbw::launch_step_batch(b->storage, b->q, p, b->total_blocks, b->stream));
-        BT_TRY(b, lbw::launch_batch_advance(b->d_state, b->d_order, p.nact, b->stream));
+        k -= run;
     }
     return LB_OK;
 }
@@ -228,7 +230,8 @@ int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots, void *d_works
     b->stream = (hipStream_t)stream;
     b->use_graph = use_graph ? 1 : 0;
     b->max_shots = max_shots;
-    b->two = lbw::step2_supported(b->storage, b->q) && scheme->steps_per_launch != 1;
+    b->ns = lbw::stepn_max(b->storage, b->q);
+    if (scheme->steps_per_launch > 0) b->ns = std::min(b->ns, scheme->steps_per_launch);
     char *ws = (char *)d_workspace;
     b->d_table = (ShotEntry *)(ws + L.table);
     b->d_state = (ShotState *)(ws + L.state);

@@ -105,7 +105,9 @@ struct StepParams {
     InterfaceParams iface;
     int32_t pre_rows = 0;              // set by launch_step: leading block rows that
                                        // do the prolong_on work
-    double s_n2 = 0.0;                 // launch_step2: source amplitude of the second step
+    double s_n2 = 0.0;                 // launch_stepn: source amplitudes of the second
+    double s_n3 = 0.0;                 // and third steps
+    int32_t nrun = 1;                  // launch_stepn: steps this launch takes (<= ns)
 };
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
@@ -174,6 +176,7 @@ struct BatchParams {
     const int64_t *wprefix = nullptr;        // [nact + 1] first two-step wave of each active shot
     const int32_t *order = nullptr;          // [nact] slot of each active shot
     int32_t nact = 0;
+    int32_t max_run = 1;                     // blocked launch: steps per shot at most
     Collision coll;
 };
 
@@ -185,20 +188,22 @@ int step_vwidth(int storage);
 int step_tile_nodes(int storage);   // x-nodes covered by one step block
 hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s);
 hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact, hipStream_t s);
-// Two-step batch launch (step2_supported configurations): every active shot
-// advances two steps, or one if one is left; then launch_batch_advance2.
-int64_t step2_waves(int storage, int q, int32_t nx, int32_t ny);
-hipError_t launch_step2_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s);
-hipError_t launch_batch_advance2(ShotState *state, const int32_t *order, int nact, hipStream_t s);
+// Blocked batch launch with the ns-step kernel: every active shot advances
+// min(ns, bp.max_run, steps left) steps; then launch_batch_advance_n with
+// run = bp.max_run.  nwaves: sum of stepn_waves over the active shots.
+int64_t stepn_waves(int storage, int q, int ns, int32_t nx, int32_t ny);
+hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp, int64_t nwaves, hipStream_t s);
+hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
-// Two pull steps in one launch: reads h(n) from p.src, writes h(n+2) to
-// p.dst (a buffer other than p.src), records columns p.rec.col and
-// p.rec.col + 1, source amplitudes p.s_n and p.s_n2.  No reduction
-// partials, rho_out, snapshot or interface work.
-hipError_t launch_step2(int storage, const StepParams &p, hipStream_t s);
+// p.nrun (<= ns) pull steps in one launch of the temporally blocked ns-step
+// kernel: reads h(n) from p.src, writes h(n + p.nrun) to p.dst (a buffer
+// other than p.src), records columns p.rec.col .. p.rec.col + p.nrun - 1,
+// source amplitudes p.s_n, p.s_n2, p.s_n3.  No reduction partials, rho_out,
+// snapshot or interface work.  2 <= ns <= stepn_max(storage, q).
+hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
+int stepn_max(int storage, int q);   // steps per launch the blocked kernel offers (1: none)
 int step2_owned_columns(int storage);
-bool step2_supported(int storage, int q);   // configurations the two-step kernel serves
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
                                double *out, hipStream_t s);

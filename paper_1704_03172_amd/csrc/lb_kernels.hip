@@ -23,7 +23,7 @@
 // This one-step kernel serves single steps (the last of a call, sum-of-rho
 // recording, checkpoint boundaries), the refinement patch, whose interface
 // work is fused into it, and the adjoint's forward recompute; runs of steps
-// go to the two-step kernel of lb_step2.hip.  Both take their per-node
+// go to the temporally blocked kernel of lb_blocked.hip.  Both take their per-node
 // arithmetic from lb_node.h.
 #include "lb_internal.h"
 #include "lb_node.h"

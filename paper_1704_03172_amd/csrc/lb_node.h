@@ -155,14 +155,24 @@ __device__ inline T cdot(int i, T jx, T jy) {
 // C = M^-1 S M applied through the non-conserved moments only.
 template <typename T, int Q, int KIND>
 __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&out)[Q], T (&w)[Q]) {
-    T rho = T(0), jx = T(0), jy = T(0);
+    // moments, each sum started from its first term (0 + x is not x for
+    // x = -0, so a 0 start would cost an addition the compiler must keep)
+    T rho = g[0], jx = T(0), jy = T(0);
+    bool hx = false, hy = false;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) rho += g[i];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rho += g[i];
-        if (cxv<Q>(i) > 0) jx += g[i];
-        if (cxv<Q>(i) < 0) jx -= g[i];
-        if (cyv<Q>(i) > 0) jy += g[i];
-        if (cyv<Q>(i) < 0) jy -= g[i];
+        if (cxv<Q>(i) != 0) {
+            const T v = cxv<Q>(i) > 0 ? g[i] : -g[i];
+            jx = hx ? jx + v : v;
+            hx = true;
+        }
+        if (cyv<Q>(i) != 0) {
+            const T v = cyv<Q>(i) > 0 ? g[i] : -g[i];
+            jy = hy ? jy + v : v;
+            hy = true;
+        }
     }
     weights<T, Q>(c2, c, w);
     T d[Q];
@@ -256,10 +266,15 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
                                  T (&out)[Q]) {
     T gs[Q], w[Q];
     collide<T, Q, KIND>(g, c2, p.coll, gs, w);
-    if (y == p.src_y && x == p.src_x) {
-        const T sn = T(s_n);
+    if (y == p.src_y) {   // uniform over a row: only the source row tests x
+        // (the empty asm keeps this a branch: otherwise the compiler turns
+        // the injection into selects evaluated at every node)
+        asm volatile("");
+        if (x == p.src_x) {
+            const T sn = T(s_n);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+            for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+        }
     }
     const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
 #pragma unroll

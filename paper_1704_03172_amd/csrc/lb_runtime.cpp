@@ -66,7 +66,7 @@ int validate(const lb_grid_desc *d) {
     if (d->ckpt_every < 0 || d->ckpt_capacity < 0) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
-    if (d->steps_per_launch < 0 || d->steps_per_launch > 1) return LB_E_RANGE;
+    if (d->steps_per_launch < 0 || d->steps_per_launch > 3) return LB_E_RANGE;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -745,16 +745,29 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
     return LB_OK;
 }
 
-// Whether the next two steps can go into one launch.
-bool two_step_ok(const lb_grid *h) {
-    if (h->d.steps_per_launch == 1 || h->patch || h->sum_rho) return false;
-    if (!lbw::step2_supported(h->storage, h->q)) return false;
-    if (h->ckpt_valid && (h->t + 2) % h->d.ckpt_every == 0) return false;   // h(t+1) must exist
-    return true;
+// Steps the next launch may take: the blocked kernel serves up to
+// stepn_max steps (capped by the descriptor's steps_per_launch), and a
+// launch from t to t+ns skips the states h(t+1) .. h(t+ns-1), so no
+// checkpoint column (whose launch pulls from h(col-1)) may fall in
+// t+2 .. t+ns.  left: steps still to take in this call; the last launch of
+// a call takes one step (the fields and the saved state of time t are read
+// from h(t-1)).
+int blocked_steps(const lb_grid *h, int64_t left) {
+    if (h->patch || h->sum_rho) return 1;
+    int ns = lbw::stepn_max(h->storage, h->q);
+    if (h->d.steps_per_launch > 0) ns = std::min(ns, h->d.steps_per_launch);
+    ns = (int)std::min<int64_t>(ns, left - 1);
+    if (h->ckpt_valid)
+        for (int k = 2; k <= ns; ++k)
+            if ((h->t + k) % h->d.ckpt_every == 0) {
+                ns = k - 1;
+                break;
+            }
+    return std::max(ns, 1);
 }
 
-// Steps t -> t+2 in one launch (columns t+1 and t+2).
-int two_steps(lb_grid *h) {
+// Steps t -> t+ns in one launch of the blocked kernel (columns t+1 .. t+ns).
+int blocked_launch(lb_grid *h, int ns) {
     const int64_t col = h->t + 1;
     if (h->ckpt_valid && col % h->d.ckpt_every == 0) {
         int rc = save_checkpoint(h, col, false);
@@ -766,11 +779,13 @@ int two_steps(lb_grid *h) {
     p.dst = g.prevp();
     p.s_n = source_at(h, col);
     p.s_n2 = source_at(h, col + 1);
+    p.s_n3 = source_at(h, col + 2);
+    p.nrun = ns;
     if (recording(h)) attach_receivers(h, g, p, col);
-    LB_TRY(h, lbw::launch_step2(h->storage, p, h->stream));
+    LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));
     g.cur = 1 - g.cur;
     g.prev_pre = 0;
-    h->t = col + 1;
+    h->t = col + ns - 1;
     return LB_OK;
 }
 
@@ -783,17 +798,14 @@ int lb_step_n(lb_grid *h, int64_t n) {
     if (h->d.ckpt_every > 0 && (h->t + n) / h->d.ckpt_every >= h->d.ckpt_capacity) return LB_E_RANGE;
     int rc;
     if (!h->collided && (rc = initial_collision(h))) return rc;
-    // the last launch of a call is a one-step launch: the fields (and the
-    // saved state) of time t are read from h(t-1), which a two-step launch
-    // does not store
     for (int64_t k = 0; k < n;) {
-        if (n - k >= 3 && two_step_ok(h)) {
-            if ((rc = two_steps(h))) return rc;
-            k += 2;
-        } else {
-            if ((rc = one_step(h))) return rc;
-            k += 1;
+        const int ns = blocked_steps(h, n - k);
+        if (ns > 1) {
+            if ((rc = blocked_launch(h, ns))) return rc;
+        } else if ((rc = one_step(h))) {
+            return rc;
         }
+        k += ns;
     }
     return LB_OK;
 }

@@ -77,7 +77,9 @@ def test_desc_layout_matches_c(lw):
     (dict(nx=256, ny=256, patch=(96, 96, 64, 64), sponge_width=100), -2),
     (dict(nx=256, ny=256, patch=(96, 96, 4, 64)), -2),
     (dict(steps_per_launch=1), 0),
-    (dict(steps_per_launch=2), -2),
+    (dict(steps_per_launch=3), 0),
+    (dict(steps_per_launch=4), -2),
+    (dict(steps_per_launch=-1), -2),
 ])
 def test_validate(lw, kw, code):
     args = dict(nx=64, ny=64)

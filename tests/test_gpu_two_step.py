@@ -1,13 +1,14 @@
-"""Two time steps per launch (temporal blocking) on the GPU.
+"""Several time steps per launch (temporal blocking) on the GPU.
 
-lb_step_n takes two steps per launch unless the sum of rho is recorded, a
-patch is present, a checkpoint falls between the two steps or the descriptor
-asks for one step per launch.  The two-step kernel must give the same bits
-as two launches of the one-step kernel: the tests below compare the two
-paths bitwise over lattices, collisions, storage formats, grid shapes that
-leave ragged wavefront strips and segments, segment heights, odd step counts
-and chunked calls, with receivers on strip and segment boundaries and on the
-periodic seam, and hold the two-step path to the FP64 oracle bars.
+lb_step_n takes up to three steps per launch (D2Q5 FP32; two for the other
+configurations) unless the sum of rho is recorded, a patch is present, a
+checkpoint falls inside the launch or the descriptor caps the steps per
+launch.  The blocked kernel must give the same bits as launches of the
+one-step kernel: the tests below compare the paths bitwise over lattices,
+collisions, storage formats, caps of 2 and 3 steps, grid shapes that leave
+ragged wavefront strips and segments, step counts of every remainder and
+chunked calls, with receivers on strip and segment boundaries and on the
+periodic seam, and hold the blocked path to the FP64 oracle bars.
 """
 import numpy as np
 import pytest
@@ -26,9 +27,9 @@ def same(a, b):
         np.testing.assert_array_equal(a["fields"][f], b["fields"][f])
 
 
-def both(case, precision, **kw):
+def both(case, precision, spl=0, **kw):
     one = run_gpu(case, precision, sum_rho=False, steps_per_launch=1)
-    two = run_gpu(case, precision, sum_rho=False, **kw)
+    two = run_gpu(case, precision, sum_rho=False, steps_per_launch=spl, **kw)
     assert np.abs(one["traces"]).max() > 0
     same(one, two)
     return two
@@ -43,8 +44,9 @@ def boundary_receivers(nx, ny):
         for k in range(1, nx // w + 1):
             xs.update({k * w - 1, k * w, k * w + 1})
     ys = {0, 1, ny - 1, ny - 2}
-    for k in range(1, ny // 8 + 1):
-        ys.update({8 * k - 1, 8 * k})
+    for h in (4, 6, 8):
+        for k in range(1, ny // h + 1):
+            ys.update({h * k - 1, h * k})
     xs = sorted(x for x in xs if 0 <= x < nx)
     ys = sorted(y for y in ys if 0 <= y < ny)
     return np.array([(x, y) for y in ys for x in xs[::3]] + [(x, ys[len(ys) // 2]) for x in xs],
@@ -57,12 +59,22 @@ SCHEMES = [(5, "bgk", None), (5, "mrt", [1, 1, 1, 1.6, 1.3]), (9, "bgk", None),
 
 @pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
 @pytest.mark.parametrize("q,collision,s", SCHEMES)
-def test_two_step_equals_one_step(precision, q, collision, s):
+@pytest.mark.parametrize("spl", [0, 2])
+def test_two_step_equals_one_step(precision, q, collision, s, spl):
     case = layered_case(700, 45, q=q, collision=collision, s=s, nsteps=61)
     case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(700, 45)])
-    two = both(case, precision)
+    two = both(case, precision, spl=spl)
     if precision != "f16s":
         compare(case, precision, gpu=two)
+
+
+@pytest.mark.parametrize("nsteps", [2, 3, 4, 5, 6, 7, 30, 31, 32])
+def test_step_count_remainders(nsteps):
+    """Every remainder of the step count modulo the steps per launch (the
+    last launch of a call takes one step)."""
+    case = layered_case(300, 30, nsteps=nsteps, sponge=2)
+    case["wavelet"] = 1e3 * case["wavelet"]
+    both(case, "f32")
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
@@ -83,16 +95,17 @@ def test_two_step_shapes(precision, nx, ny):
         compare(case, precision, gpu=two)
 
 
-@pytest.mark.parametrize("ny", [8, 9, 15, 16, 17, 23, 40])
+@pytest.mark.parametrize("ny", [6, 7, 8, 9, 12, 13, 15, 16, 17, 23, 40])
 def test_segment_edges(ny):
-    """Grid heights around multiples of the 8-row segment (ragged last
-    segment, a single segment, rows that wrap into the next segment), D2Q9
-    MRT so that every direction crosses the segment edges."""
-    case = layered_case(300, ny, q=9, collision="mrt", s=[1, 1, 1, 2, 2, 2, 1, 1, 2], nsteps=40,
-                        sponge=2)
-    case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
-    two = both(case, "f32")
-    compare(case, "f32", gpu=two)
+    """Grid heights around multiples of the segment heights (6 rows for
+    three steps, 8 and 4 for two: ragged last segment, a single segment, rows
+    that wrap into the next segment), D2Q5 (three steps) and D2Q9 MRT (two)
+    so that every direction crosses the segment edges."""
+    for q, coll, s in ((5, "bgk", None), (9, "mrt", [1, 1, 1, 2, 2, 2, 1, 1, 2])):
+        case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2)
+        case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
+        two = both(case, "f32")
+        compare(case, "f32", gpu=two)
 
 
 def test_chunked_calls_mix_one_and_two_step_launches():
