@@ -5,11 +5,12 @@ anomalies, 64-node sponge, Ricker source at >= 20 nodes per wavelength and
 256 surface receivers; D2Q5, BGK tau = 1/2, FP32 populations.  One "step" is
 one time step of the whole grid (pull-stream, moments, per-node weights,
 linear equilibrium, collision, source, sponge, receiver sampling at every
-time).  lb_step_n runs several steps per fused launch (three for this
-configuration; the last launch of a call takes one), so the dominant kernel
-is the temporally blocked kernel: it reads h(n) and writes h(n+3), 44
-algorithmic bytes per node per launch (24 read, 20 written), i.e. 14.7 bytes
-per lattice update.  Inputs are resident in HBM before the timed region.
+time).  lb_step_n runs several steps per fused launch (four for this
+configuration, as lb_blocked_steps reports; the last launch of a call takes
+one), so the dominant kernel is the temporally blocked kernel: it reads h(n)
+and writes h(n+4), 44 algorithmic bytes per node per launch (24 read, 20
+written), i.e. 11 bytes per lattice update.  Inputs are resident in HBM
+before the timed region.
 
 Prints ONE JSON line: MLUPS (value), roofline of the blocked kernel (its
 launch duration measured with HIP events as the difference of two runs that
@@ -41,13 +42,10 @@ def bytes_per_lup(q, precision):
     return 2 * q * s + c
 
 
-def max_steps_per_launch(q, precision):
-    """Steps per launch the blocked kernel offers (as the library decides)."""
-    if q == 5 and precision == "f32":
-        return 3
-    if q == 9 and precision == "f16s":
-        return 1
-    return 2
+def max_steps_per_launch(lbwave, q, collision, precision):
+    """Steps per launch the blocked kernel takes for a configuration (the
+    library's lb_blocked_steps)."""
+    return lbwave.blocked_steps(nx=64, ny=64, lattice=q, collision=collision, precision=precision)
 
 
 def launch_plan(nsteps, ns_max):
@@ -202,11 +200,12 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per blocked launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factors), or
-    None when the kernel sources changed after the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "k_stepn3_d2q5_bgk_f32_layered4096_hbm_counters.md")
+def measured_traffic(nsl):
+    """HBM bytes per blocked launch of nsl steps from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    factors), or None when the kernel sources changed after the counters
+    were taken."""
+    prof = os.path.join(ROOT, "profiles", "k_stepn%d_d2q5_bgk_f32_layered4096_hbm_counters.md" % nsl)
     try:
         text = open(prof).read()
         sha = kernel_source_sha256()
@@ -309,7 +308,7 @@ def main():
     N = wl["nx"] * wl["ny"]
     cap = steps + warmup + 1
 
-    nsl = max_steps_per_launch(5, "f32")
+    nsl = max_steps_per_launch(lbwave, 5, "bgk", "f32")
     grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + nsl * 501 + 10)
     log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
     t = time_steps(torch, grid, steps, warmup)
@@ -335,11 +334,11 @@ def main():
     if not args.no_variants:
         vsteps = 1000
         for q, coll, prec in ((5, "mrt", "f32"), (9, "bgk", "f32"), (9, "mrt", "f32"),
-                              (5, "bgk", "f64"), (5, "bgk", "f16s")):
+                              (5, "bgk", "f64"), (9, "bgk", "f64"), (5, "bgk", "f16s")):
             g = make_layered(lbwave, wl, q, coll, prec, vsteps + 11)
             tv = time_steps(torch, g, vsteps, 10)
             b = bytes_per_lup(q, prec)
-            vplan = launch_plan(vsteps, max_steps_per_launch(q, prec))
+            vplan = launch_plan(vsteps, max_steps_per_launch(lbwave, q, coll, prec))
             nb = b * N * sum(vplan.values())      # algorithmic bytes of the launches
             variants["D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())] = {
                 "MLUPS": round(N * vsteps / tv / 1e6, 1),
@@ -374,7 +373,7 @@ def main():
         _, serving["one_shot_per_launch"] = serve.run_fifo(trace)
         torch.cuda.empty_cache()
 
-    traffic = measured_traffic() if args.n == 4096 else None
+    traffic = measured_traffic(nsl) if args.n == 4096 else None
     cpu = None
     if not args.no_cpu:
         log("timing CPU oracle sample (~%.0f s)" % args.cpu_seconds)
@@ -397,6 +396,11 @@ def main():
                      "kernel": "k_stepn<float,5,BGK,%d> (%d steps per launch)" % (nsl, nsl),
                      "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": nsl * N,
                      "avg_kernel_us": round(kern_s * 1e6, 3)},
+        # the bytes a one-step-per-launch path would move per step (44 per
+        # node), over the measured time per step: temporal blocking lifts this
+        # above the HBM peak
+        "one_step_equivalent": {"GBs": round(bpl * N * steps / t / 1e9, 1),
+                                "frac_hbm": round(bpl * N * steps / t / 1e9 / HBM_PEAK_GBS, 4)},
         "launches_by_steps": {str(k): v for k, v in sorted(plan.items())},
         "copy_kernel_GBs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),

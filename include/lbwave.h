@@ -108,14 +108,16 @@ typedef struct lb_grid lb_grid;
  *                  two adjoint population sets).  0: no checkpoints.
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
  *   steps_per_launch  0 (default): lb_step_n advances several time steps
- *                  per kernel launch (temporal blocking: three for D2Q5 with
- *                  FP32 populations, two for the other configurations, one
- *                  for D2Q9 with FP16 storage) wherever it can (no patch, no
- *                  sum-rho recording, no checkpoint falling inside a launch;
- *                  the last launch of each call takes one step), which
- *                  divides the HBM traffic per step accordingly; the results
- *                  equal those of one step per launch bit for bit.  1, 2, 3:
- *                  at most that many steps per launch.
+ *                  per kernel launch (temporal blocking: four for D2Q5 and
+ *                  for D2Q9 with FP64 populations, three for D2Q9 BGK and
+ *                  two for D2Q9 MRT with FP32 populations, two for D2Q5 and
+ *                  one for D2Q9 with FP16 storage; lb_blocked_steps reports
+ *                  the count) wherever it can (no patch, no sum-rho
+ *                  recording, no checkpoint falling inside a launch; the
+ *                  last launch of each call takes one step), which divides
+ *                  the HBM traffic per step accordingly; the results equal
+ *                  those of one step per launch bit for bit.  1 .. 4: at most
+ *                  that many steps per launch.
  *   nbatch         independent shots sharing the grid shape (must be 1).
  */
 typedef struct {
@@ -149,6 +151,13 @@ void lb_default_desc(lb_grid_desc *d);
 /* Check a descriptor without a GPU.  Returns LB_OK or the error code that
  * lb_create_grid would return for it. */
 int lb_validate_desc(const lb_grid_desc *d);
+
+/* Most time steps one kernel launch of lb_step_n takes for a grid with this
+ * descriptor (temporal blocking; see steps_per_launch): the count the
+ * blocked kernel offers for the lattice, collision and precision, capped by
+ * steps_per_launch; 1 with a patch.  No GPU needed.  Returns LB_OK and
+ * writes *ns, or the error lb_validate_desc gives (LB_E_INVALID for NULL). */
+int lb_blocked_steps(const lb_grid_desc *d, int32_t *ns);
 
 /* Device bytes the workspace of a grid with this descriptor needs
  * (two population buffers, c^2, receiver tables, reduction partials and,
@@ -260,7 +269,7 @@ const char *lb_status_string(int code);
  *
  * Many independent shots (grids of different sizes, each with its own medium,
  * source, receivers and step count) advance together: one launch covers up
- * to three time steps (as the scheme's steps_per_launch allows, see
+ * to four time steps (as lb_blocked_steps gives for the scheme, see
  * lb_grid_desc) of every active shot, a shot with fewer steps left taking
  * those, and the shot's time and buffer
  * parity live in device memory, so a tick of k steps is captured once as a

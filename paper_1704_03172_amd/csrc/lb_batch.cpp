@@ -1,6 +1,6 @@
 // lb_batch.cpp -- batched executor behind the lb_batch_* calls of
 // include/lbwave.h: many independent shots of the linear LB scheme advance
-// together, up to three steps per launch (the temporally blocked kernel;
+// together, up to four steps per launch (the temporally blocked kernel;
 // one step per launch for the configuration it does not serve),
 // with per-shot time and buffer parity kept on the device so that a tick of
 // k steps is captured once as a HIP graph and replayed until the set of
@@ -230,7 +230,7 @@ int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots, void *d_works
     b->stream = (hipStream_t)stream;
     b->use_graph = use_graph ? 1 : 0;
     b->max_shots = max_shots;
-    b->ns = lbw::stepn_max(b->storage, b->q);
+    b->ns = lbw::stepn_max(b->storage, b->q, b->coll.kind);
     if (scheme->steps_per_launch > 0) b->ns = std::min(b->ns, scheme->steps_per_launch);
     char *ws = (char *)d_workspace;
     b->d_table = (ShotEntry *)(ws + L.table);

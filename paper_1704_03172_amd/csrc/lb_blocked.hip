@@ -14,8 +14,8 @@ constexpr int kAdvBlock = 256;
 
 // ---- NS time steps per launch ---------------------------------------------------
 // Temporal blocking: one pass reads h(n) and writes h(n+NS), so every
-// population element crosses HBM once per NS updates (NS = 3 for D2Q5 with
-// FP32 populations, 2 otherwise).  A wavefront owns a strip of columns and a
+// population element crosses HBM once per NS updates (NS up to 4, see
+// tn_max).  A wavefront owns a strip of columns and a
 // segment of rows: it loads the segment's rows of h(n) plus NS halo rows on
 // each side, all at once (of the outermost halo rows only the population
 // that streams into the segment), then walks down the rows computing
@@ -33,12 +33,6 @@ constexpr int kAdvBlock = 256;
 // rows and columns the wave owns are recorded.
 constexpr int kT2Block = 256;
 constexpr int kT2Halo = 4;    // halo lanes per side
-
-// Rows per segment of the two-step kernel: all segment rows plus four halo
-// rows sit in registers, so the larger states (D2Q9, FP64, FP16 storage with
-// 4 columns per lane) take shorter segments.
-template <typename S, int Q>
-constexpr int t2_rows() { return (Q == 5 && sizeof(S) == 4) ? 8 : 4; }
 
 template <typename S> struct Tb {
     static constexpr int V = sizeof(S) == 8 ? 1 : int(8 / sizeof(S));   // 8-byte lane accesses
@@ -160,24 +154,38 @@ __device__ inline void static_for(F &&f) {
     static_for_impl<B>(f, std::make_integer_sequence<int, E - B>{});
 }
 
-// One of three arrays chosen at compile time (separate arrays per stage stay
+// One of four arrays chosen at compile time (separate arrays per stage stay
 // in registers; one array of all stages would be too large to promote).
 template <int I, typename A>
-__device__ inline A &pick3(A &a0, A &a1, A &a2) {
+__device__ inline A &pick4(A &a0, A &a1, A &a2, A &a3) {
     if constexpr (I == 0) return a0;
     else if constexpr (I == 1) return a1;
-    else return a2;
+    else if constexpr (I == 2) return a2;
+    else return a3;
 }
 
-// Steps per launch the blocked kernel offers for a configuration: three for
-// D2Q5 with FP32 populations, two for the others (larger per-row state).
-template <typename S, int Q>
-constexpr int tn_max() { return (Q == 5 && sizeof(S) == 4) ? 3 : 2; }
+// Steps per launch the blocked kernel offers for a configuration: the most
+// whose per-stage row state still fits in registers without scratch memory
+// (measured at 4096^2 on MI355X, each count was faster than the one below
+// it).  1: not offered (D2Q9 with FP16 storage, whose 4-column lanes would
+// hold their rows in scratch).
+template <typename S, int Q, int KIND>
+constexpr int tn_max() {
+    if constexpr (sizeof(S) == 2) return Q == 5 ? 2 : 1;
+    else if constexpr (Q == 9 && sizeof(S) == 4) return KIND == 0 ? 3 : 2;
+    else return 4;
+}
 
-// Rows per segment for NS steps: all segment rows plus NS halo rows on each
-// side sit in registers.
+// Rows per segment for NS steps: the segment rows plus NS halo rows on each
+// side sit in registers (K = rows + 2 NS rows per stage), so more steps and
+// larger per-row states (D2Q9, FP16 storage with 4 columns per lane) take
+// shorter segments.
 template <typename S, int Q, int NS>
-constexpr int tn_rows() { return NS == 3 ? 6 : t2_rows<S, Q>(); }
+constexpr int tn_rows() {
+    if constexpr (NS == 2 && Q == 5 && sizeof(S) == 4) return 8;
+    else if constexpr (NS == 3 && Q == 5) return 6;
+    else return 4;
+}
 
 // Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch; wib: the
 // wave's index in its block.  The wave takes nrun <= NS steps: stage s
@@ -210,7 +218,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
     const S *src = reinterpret_cast<const S *>(p.src);
     S *dst = reinterpret_cast<S *>(p.dst);
     const T *c2 = reinterpret_cast<const T *>(p.c2);
-    const double sn[3] = {p.s_n, p.s_n2, p.s_n3};
+    const double sn[4] = {p.s_n, p.s_n2, p.s_n3, p.s_n4};
 
     // L0[k]: row y0 - NS + k (wrapped) of h(n), all rows loaded at once;
     // L1[k], L2[k]: the same row of h(n+1), h(n+2).  Rows that the neighbouring segments
@@ -219,7 +227,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
     // second finds them in L2; the others stream (nontemporal).  Of the
     // outermost rows only the populations that stream into the segment are
     // needed.
-    T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], C[K][V];
+    T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], L3[K][Q][V], C[K][V];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t ro = (int64_t)wrapi(y0 - NS + k, ny) * nx;
@@ -253,7 +261,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
         const int gm = y0 - NS + m;   // unwrapped row
         const bool owned_row = gm >= y0 && gm < y1;
         if (st == nrun && !owned_row) return;   // the last stage computes owned rows only
-        auto &A = pick3<st - 1>(L0, L1, L2);
+        auto &A = pick4<st - 1>(L0, L1, L2, L3);
         const int wm = wrapi(gm, ny);
         T g[Q][V];
         pull_row2<T, Q, V>(A[m - 1], A[m], A[m + 1], g);
@@ -298,7 +306,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
                 }
             }
         } else if constexpr (st < NS) {
-            auto &B = pick3<st>(L0, L1, L2);
+            auto &B = pick4<st>(L0, L1, L2, L3);
 #pragma unroll
             for (int i = 0; i < Q; ++i)
 #pragma unroll
@@ -315,6 +323,8 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
             stage(std::integral_constant<int, 2>{}, std::integral_constant<int, k - 2>{});
         if constexpr (NS >= 3 && k - 3 >= 3 && k - 3 <= K - 4)
             stage(std::integral_constant<int, 3>{}, std::integral_constant<int, k - 3>{});
+        if constexpr (NS >= 4 && k - 4 >= 4 && k - 4 <= K - 5)
+            stage(std::integral_constant<int, 4>{}, std::integral_constant<int, k - 4>{});
     });
 }
 
@@ -359,6 +369,7 @@ __global__ __launch_bounds__(kT2Block) void k_stepn_batch(BatchParams bp) {
     p.s_n = tn < e.wavelet_len ? e.wavelet[tn] : 0.0;
     p.s_n2 = tn + 1 < e.wavelet_len ? e.wavelet[tn + 1] : 0.0;
     p.s_n3 = tn + 2 < e.wavelet_len ? e.wavelet[tn + 2] : 0.0;
+    p.s_n4 = tn + 3 < e.wavelet_len ? e.wavelet[tn + 3] : 0.0;
     p.rec = e.rec;
     p.rec.col = tn;
     const int nrun = (int)min<int64_t>(min(NS, bp.max_run), ss.t_end - ss.t);
@@ -382,80 +393,107 @@ __global__ __launch_bounds__(kAdvBlock) void k_batch_advance_n(ShotState *state,
 
 }  // namespace
 
-template <typename S, int NS>
-static hipError_t stepn_dispatch(const StepParams &p, hipStream_t s) {
-    constexpr int OW = Tb<S>::OW;
-    const int ly = p.q == 5 ? tn_rows<S, 5, NS>() : tn_rows<S, 9, NS>();
-    const int64_t waves = (int64_t)((p.nx + OW - 1) / OW) * ((p.ny + ly - 1) / ly);
-    dim3 grid((unsigned)((waves + kT2Block / 64 - 1) / (kT2Block / 64)));
-    const int kind = p.coll.kind;
-    // vector accesses need every lane's columns contiguous after the wrap
-    const bool vec = p.nx % Tb<S>::V == 0;
-#define LBW_LN(QQ, KK)                                                                             \
-    do {                                                                                           \
-        if (vec) hipLaunchKernelGGL((k_stepn<S, QQ, KK, true, NS>), grid, dim3(kT2Block), 0, s, p);   \
-        else hipLaunchKernelGGL((k_stepn<S, QQ, KK, false, NS>), grid, dim3(kT2Block), 0, s, p);      \
-    } while (0)
-    if (p.q == 5) { if (kind == 0) LBW_LN(5, 0); else LBW_LN(5, 1); }
-    else if constexpr (sizeof(S) != 2 && NS == 2) { if (kind == 0) LBW_LN(9, 0); else LBW_LN(9, 1); }
-    else return hipErrorInvalidValue;   // not offered: see stepn_max
-#undef LBW_LN
-    return hipGetLastError();
+// f(S(), integral_constant<int, Q>()) for the storage format and lattice.
+template <typename F>
+static auto by_config(int storage, int q, F &&f) {
+    using Q5 = std::integral_constant<int, 5>;
+    using Q9 = std::integral_constant<int, 9>;
+    if (storage == ST_F64) return q == 5 ? f(double(), Q5()) : f(double(), Q9());
+    if (storage == ST_F16) return q == 5 ? f(_Float16(), Q5()) : f(_Float16(), Q9());
+    return q == 5 ? f(float(), Q5()) : f(float(), Q9());
 }
 
-int stepn_max(int storage, int q) {
-    if (storage == ST_F16 && q == 9) return 1;   // would hold its 4-column lanes' rows in scratch
-    if (storage == ST_F32) return q == 5 ? tn_max<float, 5>() : tn_max<float, 9>();
-    if (storage == ST_F64) return q == 5 ? tn_max<double, 5>() : tn_max<double, 9>();
-    return tn_max<_Float16, 5>();
-}
-
-hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s) {
-    if (p.nx < 1 || p.ny < 1 || ns < 2 || ns > stepn_max(storage, p.q) || p.nrun < 1 || p.nrun > ns)
-        return hipErrorInvalidValue;
-    switch (storage) {
-    case ST_F32: return ns == 3 ? stepn_dispatch<float, 3>(p, s) : stepn_dispatch<float, 2>(p, s);
-    case ST_F64: return stepn_dispatch<double, 2>(p, s);
-    case ST_F16: return stepn_dispatch<_Float16, 2>(p, s);
-    }
+// f(integral_constant<int, ns>()) for 2 <= ns <= the largest tn_max<S, Q, KIND>
+// over both collision kinds (else hipErrorInvalidValue); only those step
+// counts are instantiated.
+template <typename S, int Q, typename F>
+static hipError_t by_steps(int ns, F &&f) {
+    constexpr int m = tn_max<S, Q, 0>() > tn_max<S, Q, 1>() ? tn_max<S, Q, 0>() : tn_max<S, Q, 1>();
+    if constexpr (m >= 4) if (ns == 4) return f(std::integral_constant<int, 4>());
+    if constexpr (m >= 3) if (ns == 3) return f(std::integral_constant<int, 3>());
+    if constexpr (m >= 2) if (ns == 2) return f(std::integral_constant<int, 2>());
     return hipErrorInvalidValue;
 }
 
+template <typename S, int Q>
+static int64_t waves_of(int ns, int32_t nx, int32_t ny) {
+    int ly = 1;
+    by_steps<S, Q>(ns, [&](auto nc) { ly = tn_rows<S, Q, decltype(nc)::value>(); return hipSuccess; });
+    return (int64_t)((nx + Tb<S>::OW - 1) / Tb<S>::OW) * ((ny + ly - 1) / ly);
+}
+
+int stepn_max(int storage, int q, int kind) {
+    return by_config(storage, q, [&](auto sv, auto qc) {
+        using S = decltype(sv);
+        constexpr int Q = decltype(qc)::value;
+        return kind == 1 ? tn_max<S, Q, 1>() : tn_max<S, Q, 0>();
+    });
+}
+
 int64_t stepn_waves(int storage, int q, int ns, int32_t nx, int32_t ny) {
-    int ow, ly;
-    if (storage == ST_F32) {
-        ow = Tb<float>::OW;
-        ly = ns == 3 ? tn_rows<float, 5, 3>() : (q == 5 ? tn_rows<float, 5, 2>() : tn_rows<float, 9, 2>());
-    } else if (storage == ST_F64) {
-        ow = Tb<double>::OW;
-        ly = q == 5 ? tn_rows<double, 5, 2>() : tn_rows<double, 9, 2>();
-    } else {
-        ow = Tb<_Float16>::OW;
-        ly = tn_rows<_Float16, 5, 2>();
-    }
-    return (int64_t)((nx + ow - 1) / ow) * ((ny + ly - 1) / ly);
+    return by_config(storage, q, [&](auto sv, auto qc) {
+        return waves_of<decltype(sv), decltype(qc)::value>(ns, nx, ny);
+    });
+}
+
+hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s) {
+    if (p.nx < 1 || p.ny < 1 || (p.q != 5 && p.q != 9) || ns < 2 || ns > stepn_max(storage, p.q, p.coll.kind) ||
+        p.nrun < 1 || p.nrun > ns)
+        return hipErrorInvalidValue;
+    return by_config(storage, p.q, [&](auto sv, auto qc) {
+        using S = decltype(sv);
+        constexpr int Q = decltype(qc)::value;
+        const dim3 grid((unsigned)((waves_of<S, Q>(ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
+        // vector accesses need every lane's columns contiguous after the wrap
+        const bool vec = p.nx % Tb<S>::V == 0, mrt = p.coll.kind == 1;
+        return by_steps<S, Q>(ns, [&](auto nc) {
+            constexpr int NS = decltype(nc)::value;
+            if constexpr (NS <= tn_max<S, Q, 1>()) {
+                if (mrt) {
+                    if (vec) hipLaunchKernelGGL((k_stepn<S, Q, 1, true, NS>), grid, dim3(kT2Block), 0, s, p);
+                    else hipLaunchKernelGGL((k_stepn<S, Q, 1, false, NS>), grid, dim3(kT2Block), 0, s, p);
+                    return hipGetLastError();
+                }
+            }
+            if constexpr (NS <= tn_max<S, Q, 0>()) {
+                if (!mrt) {
+                    if (vec) hipLaunchKernelGGL((k_stepn<S, Q, 0, true, NS>), grid, dim3(kT2Block), 0, s, p);
+                    else hipLaunchKernelGGL((k_stepn<S, Q, 0, false, NS>), grid, dim3(kT2Block), 0, s, p);
+                    return hipGetLastError();
+                }
+            }
+            return hipErrorInvalidValue;
+        });
+    });
 }
 
 hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp, int64_t nwaves, hipStream_t s) {
     if (nwaves <= 0 || bp.nact <= 0) return hipSuccess;
-    if (ns < 2 || ns > stepn_max(storage, q) || bp.max_run < 1 || bp.max_run > ns) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    if ((q != 5 && q != 9) || ns < 2 || ns > stepn_max(storage, q, bp.coll.kind) || bp.max_run < 1 ||
+        bp.max_run > ns)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
     const bool mrt = bp.coll.kind == 1;
-#define LBW_BN(SS, QQ, NN)                                                                             \
-    do {                                                                                               \
-        if (mrt) hipLaunchKernelGGL((k_stepn_batch<SS, QQ, 1, NN>), grid, dim3(kT2Block), 0, s, bp);   \
-        else hipLaunchKernelGGL((k_stepn_batch<SS, QQ, 0, NN>), grid, dim3(kT2Block), 0, s, bp);       \
-    } while (0)
-    if (storage == ST_F32) {
-        if (q == 5) { if (ns == 3) LBW_BN(float, 5, 3); else LBW_BN(float, 5, 2); }
-        else LBW_BN(float, 9, 2);
-    } else if (storage == ST_F64) {
-        if (q == 5) LBW_BN(double, 5, 2); else LBW_BN(double, 9, 2);
-    } else {
-        LBW_BN(_Float16, 5, 2);
-    }
-#undef LBW_BN
-    return hipGetLastError();
+    return by_config(storage, q, [&](auto sv, auto qc) {
+        using S = decltype(sv);
+        constexpr int Q = decltype(qc)::value;
+        return by_steps<S, Q>(ns, [&](auto nc) {
+            constexpr int NS = decltype(nc)::value;
+            if constexpr (NS <= tn_max<S, Q, 1>()) {
+                if (mrt) {
+                    hipLaunchKernelGGL((k_stepn_batch<S, Q, 1, NS>), grid, dim3(kT2Block), 0, s, bp);
+                    return hipGetLastError();
+                }
+            }
+            if constexpr (NS <= tn_max<S, Q, 0>()) {
+                if (!mrt) {
+                    hipLaunchKernelGGL((k_stepn_batch<S, Q, 0, NS>), grid, dim3(kT2Block), 0, s, bp);
+                    return hipGetLastError();
+                }
+            }
+            return hipErrorInvalidValue;
+        });
+    });
 }
 
 hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s) {
@@ -463,10 +501,6 @@ hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int na
     hipLaunchKernelGGL(k_batch_advance_n, dim3((unsigned)((nact + kAdvBlock - 1) / kAdvBlock)), dim3(kAdvBlock), 0,
                        s, state, order, nact, run);
     return hipGetLastError();
-}
-
-int step2_owned_columns(int storage) {
-    return storage == ST_F32 ? Tb<float>::OW : storage == ST_F64 ? Tb<double>::OW : Tb<_Float16>::OW;
 }
 
 }  // namespace lbw

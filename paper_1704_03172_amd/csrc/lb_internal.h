@@ -105,8 +105,9 @@ struct StepParams {
     InterfaceParams iface;
     int32_t pre_rows = 0;              // set by launch_step: leading block rows that
                                        // do the prolong_on work
-    double s_n2 = 0.0;                 // launch_stepn: source amplitudes of the second
-    double s_n3 = 0.0;                 // and third steps
+    double s_n2 = 0.0;                 // launch_stepn: source amplitudes of the second,
+    double s_n3 = 0.0;                 // third and fourth steps
+    double s_n4 = 0.0;
     int32_t nrun = 1;                  // launch_stepn: steps this launch takes (<= ns)
 };
 
@@ -173,7 +174,7 @@ struct BatchParams {
     const ShotEntry *table = nullptr;        // [max_shots]
     ShotState *state = nullptr;              // [max_shots]
     const int64_t *prefix = nullptr;         // [nact + 1] first block of each active shot
-    const int64_t *wprefix = nullptr;        // [nact + 1] first two-step wave of each active shot
+    const int64_t *wprefix = nullptr;        // [nact + 1] first blocked-kernel wave of each active shot
     const int32_t *order = nullptr;          // [nact] slot of each active shot
     int32_t nact = 0;
     int32_t max_run = 1;                     // blocked launch: steps per shot at most
@@ -199,11 +200,10 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull,
 // p.nrun (<= ns) pull steps in one launch of the temporally blocked ns-step
 // kernel: reads h(n) from p.src, writes h(n + p.nrun) to p.dst (a buffer
 // other than p.src), records columns p.rec.col .. p.rec.col + p.nrun - 1,
-// source amplitudes p.s_n, p.s_n2, p.s_n3.  No reduction partials, rho_out,
-// snapshot or interface work.  2 <= ns <= stepn_max(storage, q).
+// source amplitudes p.s_n .. p.s_n4.  No reduction partials, rho_out,
+// snapshot or interface work.  2 <= ns <= stepn_max(storage, p.q, p.coll.kind).
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
-int stepn_max(int storage, int q);   // steps per launch the blocked kernel offers (1: none)
-int step2_owned_columns(int storage);
+int stepn_max(int storage, int q, int kind);   // steps per launch the blocked kernel offers (1: none)
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
                                double *out, hipStream_t s);

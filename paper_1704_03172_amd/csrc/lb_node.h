@@ -1,5 +1,5 @@
 // lb_node.h -- the per-node arithmetic of the linear LB step shared by every
-// step kernel (one step per launch, two steps per launch, the batched
+// step kernel (one step per launch, several steps per launch, the batched
 // executor, the refinement interface): lattice tables, storage traits, the
 // collision, source, sponge and receiver recording of one node.  Device
 // code only; included by the kernel sources (not part of the public
@@ -12,8 +12,8 @@
 
 // No automatic a*b+c contraction in this file: where the compiler forms fused
 // multiply-adds depends on the surrounding code, so the same per-node
-// arithmetic inlined into different kernels (one step per launch, two steps
-// per launch, the batched executor) could round differently.  The fused
+// arithmetic inlined into different kernels (one step per launch, several
+// steps per launch, the batched executor) could round differently.  The fused
 // multiply-adds of the collision are written out (fmaT) instead.
 #pragma clang fp contract(off)
 

@@ -66,7 +66,7 @@ int validate(const lb_grid_desc *d) {
     if (d->ckpt_every < 0 || d->ckpt_capacity < 0) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
-    if (d->steps_per_launch < 0 || d->steps_per_launch > 3) return LB_E_RANGE;
+    if (d->steps_per_launch < 0 || d->steps_per_launch > 4) return LB_E_RANGE;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -578,6 +578,17 @@ void lb_default_desc(lb_grid_desc *d) {
 
 int lb_validate_desc(const lb_grid_desc *d) { return validate(d); }
 
+int lb_blocked_steps(const lb_grid_desc *d, int32_t *ns) {
+    if (!d || !ns) return LB_E_INVALID;
+    int rc = validate(d);
+    if (rc) return rc;
+    int m = lbw::stepn_max(storage_kind(d->precision), d->lattice, d->collision);
+    if (d->patch_enable) m = 1;
+    if (d->steps_per_launch > 0) m = std::min(m, (int)d->steps_per_launch);
+    *ns = m;
+    return LB_OK;
+}
+
 size_t lb_workspace_bytes(const lb_grid_desc *d) {
     if (validate(d) != LB_OK) return 0;
     return make_layout(d).total;
@@ -754,7 +765,7 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
 // from h(t-1)).
 int blocked_steps(const lb_grid *h, int64_t left) {
     if (h->patch || h->sum_rho) return 1;
-    int ns = lbw::stepn_max(h->storage, h->q);
+    int ns = lbw::stepn_max(h->storage, h->q, h->d.collision);
     if (h->d.steps_per_launch > 0) ns = std::min(ns, h->d.steps_per_launch);
     ns = (int)std::min<int64_t>(ns, left - 1);
     if (h->ckpt_valid)
@@ -780,6 +791,7 @@ int blocked_launch(lb_grid *h, int ns) {
     p.s_n = source_at(h, col);
     p.s_n2 = source_at(h, col + 1);
     p.s_n3 = source_at(h, col + 2);
+    p.s_n4 = source_at(h, col + 3);
     p.nrun = ns;
     if (recording(h)) attach_receivers(h, g, p, col);
     LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));

@@ -24,7 +24,7 @@ FIELD_ORDER = ("p", "rho", "jx", "jy")
 COLLISION = {"bgk": 0, "mrt": 1}
 
 # every symbol the header declares (the ABI test checks the export table)
-EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_workspace_bytes",
+EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_blocked_steps", "lb_workspace_bytes",
            "lb_create_grid", "lb_destroy_grid", "lb_set_medium",
            "lb_set_medium_fine", "lb_set_state", "lb_set_state_fine",
            "lb_set_source", "lb_record", "lb_record_sum_rho", "lb_step_n",
@@ -90,6 +90,7 @@ def lib():
     sig = {
         "lb_default_desc": (None, [PD]),
         "lb_validate_desc": (ctypes.c_int, [PD]),
+        "lb_blocked_steps": (ctypes.c_int, [PD, ctypes.POINTER(ctypes.c_int32)]),
         "lb_workspace_bytes": (ctypes.c_size_t, [PD]),
         "lb_create_grid": (ctypes.c_int, [PD, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
         "lb_destroy_grid": (ctypes.c_int, [vp]),
@@ -175,6 +176,14 @@ def workspace_bytes(**kw):
 def validate(**kw):
     d = make_desc(**kw)
     return int(lib().lb_validate_desc(ctypes.byref(d)))
+
+
+def blocked_steps(**kw):
+    """Most time steps one launch of lb_step_n takes for this descriptor."""
+    d = make_desc(**kw)
+    ns = ctypes.c_int32()
+    _check(lib().lb_blocked_steps(ctypes.byref(d), ctypes.byref(ns)), "lb_blocked_steps")
+    return int(ns.value)
 
 
 class Grid:
@@ -370,9 +379,9 @@ def shot_desc(nx, ny, src, nsteps, nrec, sponge_width=0, sponge_sigma_max=0.0):
 
 
 class Batch:
-    """Batched executor: many shots advance together, two steps per launch
-    (steps_per_launch=1: one), captured as a HIP graph per tick (lb_batch_*
-    calls).
+    """Batched executor: many shots advance together, several steps per
+    launch (as lb_blocked_steps gives; steps_per_launch caps it), captured as
+    a HIP graph per tick (lb_batch_* calls).
 
     Runs on its own (default-priority) stream so that ticks can be captured.
     """

@@ -152,7 +152,7 @@ class ShotServer:
 
 def run_fifo(trace, precision="f32", keep_traces=False, progress=False):
     """Baseline: one shot at a time in arrival order, through the
-    single-grid lb_step_n path (two steps per launch, no batching)."""
+    single-grid lb_step_n path (several steps per launch, no batching)."""
     import torch
     from . import inputs, lbwave
     done = []

@@ -78,7 +78,8 @@ def test_desc_layout_matches_c(lw):
     (dict(nx=256, ny=256, patch=(96, 96, 4, 64)), -2),
     (dict(steps_per_launch=1), 0),
     (dict(steps_per_launch=3), 0),
-    (dict(steps_per_launch=4), -2),
+    (dict(steps_per_launch=4), 0),
+    (dict(steps_per_launch=5), -2),
     (dict(steps_per_launch=-1), -2),
 ])
 def test_validate(lw, kw, code):
@@ -87,6 +88,24 @@ def test_validate(lw, kw, code):
     assert lw.validate(**args) == code
     nb = lw.workspace_bytes(**args)
     assert (nb > 0) == (code == 0)
+
+
+@pytest.mark.parametrize("q,coll,prec,ns", [
+    (5, "bgk", "f32", 4), (5, "mrt", "f32", 4), (5, "bgk", "f64", 4), (5, "mrt", "f16s", 2),
+    (9, "bgk", "f32", 3), (9, "mrt", "f32", 2), (9, "mrt", "f64", 4), (9, "bgk", "f16s", 1)])
+def test_blocked_steps(lw, q, coll, prec, ns):
+    """Steps per launch of lb_step_n for each configuration, the cap of
+    steps_per_launch, one step with a patch, and the validation errors."""
+    kw = dict(nx=64, ny=64, lattice=q, collision=coll, precision=prec, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])
+    assert lw.blocked_steps(**kw) == ns
+    for cap in (1, 2, 3, 4):
+        assert lw.blocked_steps(steps_per_launch=cap, **kw) == min(cap, ns)
+    kw.update(nx=256, ny=256)
+    if lw.validate(patch=(96, 96, 64, 64), **kw) == 0:   # patches take D2Q5
+        assert lw.blocked_steps(patch=(96, 96, 64, 64), **kw) == 1
+    with pytest.raises(lw.LBError):
+        lw.blocked_steps(steps_per_launch=5, **kw)
+    assert lw.lib().lb_blocked_steps(None, None) == -1
 
 
 def test_workspace_accounting(lw):

@@ -1,14 +1,15 @@
 """Several time steps per launch (temporal blocking) on the GPU.
 
-lb_step_n takes up to three steps per launch (D2Q5 FP32; two for the other
-configurations) unless the sum of rho is recorded, a patch is present, a
+lb_step_n takes up to four steps per launch (as lb_blocked_steps reports for
+the configuration) unless the sum of rho is recorded, a patch is present, a
 checkpoint falls inside the launch or the descriptor caps the steps per
 launch.  The blocked kernel must give the same bits as launches of the
 one-step kernel: the tests below compare the paths bitwise over lattices,
 collisions, storage formats, caps of 2 and 3 steps, grid shapes that leave
-ragged wavefront strips and segments, step counts of every remainder and
-chunked calls, with receivers on strip and segment boundaries and on the
-periodic seam, and hold the blocked path to the FP64 oracle bars.
+ragged wavefront strips and segments (of 4, 6 and 8 rows), step counts of
+every remainder and chunked calls, with receivers on strip and segment
+boundaries and on the periodic seam, and hold the blocked path to the FP64
+oracle bars.
 """
 import numpy as np
 import pytest
@@ -59,7 +60,7 @@ SCHEMES = [(5, "bgk", None), (5, "mrt", [1, 1, 1, 1.6, 1.3]), (9, "bgk", None),
 
 @pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
 @pytest.mark.parametrize("q,collision,s", SCHEMES)
-@pytest.mark.parametrize("spl", [0, 2])
+@pytest.mark.parametrize("spl", [0, 2, 3])
 def test_two_step_equals_one_step(precision, q, collision, s, spl):
     case = layered_case(700, 45, q=q, collision=collision, s=s, nsteps=61)
     case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(700, 45)])
@@ -68,10 +69,10 @@ def test_two_step_equals_one_step(precision, q, collision, s, spl):
         compare(case, precision, gpu=two)
 
 
-@pytest.mark.parametrize("nsteps", [2, 3, 4, 5, 6, 7, 30, 31, 32])
+@pytest.mark.parametrize("nsteps", [2, 3, 4, 5, 6, 7, 8, 9, 30, 31, 32, 33])
 def test_step_count_remainders(nsteps):
-    """Every remainder of the step count modulo the steps per launch (the
-    last launch of a call takes one step)."""
+    """Every remainder of the step count modulo the four steps per launch
+    (the last launch of a call takes one step)."""
     case = layered_case(300, 30, nsteps=nsteps, sponge=2)
     case["wavelet"] = 1e3 * case["wavelet"]
     both(case, "f32")
@@ -95,17 +96,22 @@ def test_two_step_shapes(precision, nx, ny):
         compare(case, precision, gpu=two)
 
 
-@pytest.mark.parametrize("ny", [6, 7, 8, 9, 12, 13, 15, 16, 17, 23, 40])
+@pytest.mark.parametrize("ny", [3, 4, 5, 6, 7, 8, 9, 12, 13, 15, 16, 17, 23, 40])
 def test_segment_edges(ny):
-    """Grid heights around multiples of the segment heights (6 rows for
-    three steps, 8 and 4 for two: ragged last segment, a single segment, rows
-    that wrap into the next segment), D2Q5 (three steps) and D2Q9 MRT (two)
-    so that every direction crosses the segment edges."""
-    for q, coll, s in ((5, "bgk", None), (9, "mrt", [1, 1, 1, 2, 2, 2, 1, 1, 2])):
-        case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2)
+    """Grid heights around multiples of the segment heights (ragged last
+    segment, a single segment, rows that wrap into the next segment and
+    grids shorter than the halo): D2Q5 FP32 with four steps (4-row
+    segments), three (6 rows) and two (8 rows), D2Q5 FP64 with four, D2Q9
+    BGK FP32 with three and D2Q9 MRT FP32 with two (4 rows), so that every
+    direction crosses the segment edges."""
+    mrt9 = [1, 1, 1, 2, 2, 2, 1, 1, 2]
+    for q, coll, s, prec, spl in ((5, "bgk", None, "f32", 0), (5, "bgk", None, "f32", 3),
+                                  (5, "bgk", None, "f32", 2), (5, "mrt", [1, 1, 1, 1.6, 1.3], "f64", 0),
+                                  (9, "bgk", None, "f32", 0), (9, "mrt", mrt9, "f32", 0)):
+        case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2 if ny > 4 else 0)
         case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
-        two = both(case, "f32")
-        compare(case, "f32", gpu=two)
+        two = both(case, prec, spl=spl)
+        compare(case, prec, gpu=two)
 
 
 def test_chunked_calls_mix_one_and_two_step_launches():
