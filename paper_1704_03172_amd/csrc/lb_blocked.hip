@@ -187,11 +187,12 @@ constexpr int tn_rows() {
     else return 4;
 }
 
-// Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch; wib: the
-// wave's index in its block.  The wave takes nrun <= NS steps: stage s
-// (1..nrun) computes h(n+s) from h(n+s-1); the state of stage nrun is stored.
-template <typename S, int Q, int KIND, bool VEC, int NS>
-__device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nrun) {
+// Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch.  The
+// wave takes nrun <= NS steps (FULL: NS, known at compile time): stage s
+// (1..nrun) computes h(n+s) from h(n+s-1); the state of stage nrun is
+// stored.
+template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL>
+__device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     using T = typename Tr<S>::T;
     constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS>(), K = LY + 2 * NS;
     static_assert(H * V >= NS, "the strip halo must cover one column per step");
@@ -211,7 +212,13 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
         xw[j] = wrapi(xl + j, nx);
         own[j] = own_lane && xl + j < nx;
     }
+    const int nrun = FULL ? NS : nrun_arg;
     const int xv = xw[0];   // VEC: the lane's columns are xv .. xv + V - 1
+    // whether any column of the strip (halo lanes included, before the wrap)
+    // lies within the sponge width of a side edge: else the sponge depends
+    // on the row alone
+    const int L = p.sponge_width;
+    const bool strip_sponge = sx * OW - H * V < L || sx * OW - H * V + 64 * V - 1 >= nx - L;
     int dxw[V];             // distance of each column to the nearest side edge
 #pragma unroll
     for (int j = 0; j < V; ++j) dxw[j] = min(xw[j], nx - 1 - xw[j]);
@@ -227,6 +234,13 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
     // second finds them in L2; the others stream (nontemporal).  Of the
     // outermost rows only the populations that stream into the segment are
     // needed.
+    // this segment's slice of the receiver row table: lane k holds
+    // row_ptr[y0 + k], read back per row with readlane (loaded before the
+    // rows so that its wait does not hold the arithmetic behind them)
+    const bool has_rec = p.rec.row_ptr != nullptr;
+    int rowv = 0;
+    if (has_rec && lane <= y1 - y0) rowv = p.rec.row_ptr[y0 + lane];
+
     T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], L3[K][Q][V], C[K][V];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -243,15 +257,6 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
             load_c2row<VEC, false, T, V>(c2, ro, xv, xw, C[k]);
         }
     }
-    // this segment's slice of the receiver row table, in LDS (a vector-memory
-    // load of it would make the arithmetic below wait for every row load)
-    __shared__ int32_t s_rows[kT2Block / 64][LY + 1];
-    int32_t *rows = s_rows[wib];
-    const bool has_rec = p.rec.row_ptr != nullptr;
-    if (has_rec) {
-        if (lane <= y1 - y0) rows[lane] = p.rec.row_ptr[y0 + lane];
-        __builtin_amdgcn_wave_barrier();
-    }
 
     // stage st (1..NS) at row m: h(n+st) from rows m-1, m, m+1 of h(n+st-1)
     auto stage = [&](auto stc, auto mc) __attribute__((always_inline)) {
@@ -267,8 +272,8 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
         pull_row2<T, Q, V>(A[m - 1], A[m], A[m + 1], g);
         int rb = 0, re = 0;
         if (has_rec && owned_row) {
-            rb = rows[gm - y0];
-            re = rows[gm - y0 + 1];
+            rb = __builtin_amdgcn_readlane(rowv, m - NS);
+            re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
         }
         Receivers rc = p.rec;
         rc.col = p.rec.col + st - 1;
@@ -279,7 +284,8 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int wib, int nr
 #pragma unroll
             for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
             if (rb < re && own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, C[m][j]);
-            post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), sn[st - 1], pj);
+            post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), sn[st - 1], pj,
+                                  strip_sponge || min(wm, ny - 1 - wm) < L);
             // rounded to the storage format, as a stored h(n+st) would be
 #pragma unroll
             for (int i = 0; i < Q; ++i) po[i][j] = T(to_store<S>(pj[i]));
@@ -332,7 +338,7 @@ template <typename S, int Q, int KIND, bool VEC, int NS>
 __global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
     // wave-uniform (so that the row and loop arithmetic is scalar)
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    stepn_wave<S, Q, KIND, VEC, NS>(p, xcd_block() * (kT2Block / 64) + wib, wib, p.nrun);
+    stepn_wave<S, Q, KIND, VEC, NS, true>(p, xcd_block() * (kT2Block / 64) + wib, NS);
 }
 
 // Up to NS steps of every active shot in one launch (a shot takes
@@ -374,8 +380,8 @@ __global__ __launch_bounds__(kT2Block) void k_stepn_batch(BatchParams bp) {
     p.rec.col = tn;
     const int nrun = (int)min<int64_t>(min(NS, bp.max_run), ss.t_end - ss.t);
     const int lw = int(w - bp.wprefix[lo]);
-    if (e.nx % Tb<S>::V == 0) stepn_wave<S, Q, KIND, true, NS>(p, lw, wib, nrun);
-    else stepn_wave<S, Q, KIND, false, NS>(p, lw, wib, nrun);
+    if (e.nx % Tb<S>::V == 0) stepn_wave<S, Q, KIND, true, NS, false>(p, lw, nrun);
+    else stepn_wave<S, Q, KIND, false, NS, false>(p, lw, nrun);
 }
 
 // After a blocked batch launch of up to `run` steps: each active shot
@@ -438,7 +444,7 @@ int64_t stepn_waves(int storage, int q, int ns, int32_t nx, int32_t ny) {
 
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s) {
     if (p.nx < 1 || p.ny < 1 || (p.q != 5 && p.q != 9) || ns < 2 || ns > stepn_max(storage, p.q, p.coll.kind) ||
-        p.nrun < 1 || p.nrun > ns)
+        p.nrun != ns)
         return hipErrorInvalidValue;
     return by_config(storage, p.q, [&](auto sv, auto qc) {
         using S = decltype(sv);

@@ -108,7 +108,7 @@ struct StepParams {
     double s_n2 = 0.0;                 // launch_stepn: source amplitudes of the second,
     double s_n3 = 0.0;                 // third and fourth steps
     double s_n4 = 0.0;
-    int32_t nrun = 1;                  // launch_stepn: steps this launch takes (<= ns)
+    int32_t nrun = 1;                  // launch_stepn: steps this launch takes (= ns)
 };
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
@@ -197,9 +197,9 @@ hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp,
 hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
-// p.nrun (<= ns) pull steps in one launch of the temporally blocked ns-step
-// kernel: reads h(n) from p.src, writes h(n + p.nrun) to p.dst (a buffer
-// other than p.src), records columns p.rec.col .. p.rec.col + p.nrun - 1,
+// ns pull steps in one launch of the temporally blocked ns-step kernel
+// (p.nrun must equal ns): reads h(n) from p.src, writes h(n + ns) to p.dst
+// (a buffer other than p.src), records columns p.rec.col .. p.rec.col + ns - 1,
 // source amplitudes p.s_n .. p.s_n4.  No reduction partials, rho_out,
 // snapshot or interface work.  2 <= ns <= stepn_max(storage, p.q, p.coll.kind).
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);

@@ -125,27 +125,28 @@ __device__ inline void store_x(S *__restrict__ row, int x0, int nx, const S (&v)
 // ---- the per-node update ---------------------------------------------------
 // Lattice weights from c^2 (Sec. II C): D2Q5 w_i = c^2/2 for movers,
 // w0 = 1 - 2 c^2; D2Q9 w1 = c^2 kax, w5 = r w1, w0 = 1 - 4 w1 - 4 w5.
+// (1 - 4 w1 as one fused multiply-add: 4 w1 is exact, so this is the
+// rounding of 1 - 4 w1 either way.)
 template <typename T, int Q>
 __device__ inline void weights(T c2, const Collision &c, T (&w)[Q]) {
     if (Q == 5) {
         T w1 = T(0.5) * c2;
-        w[0] = T(1) - T(4) * w1;
+        w[0] = fmaT(T(-4), w1, T(1));
 #pragma unroll
         for (int i = 1; i < Q; ++i) w[i] = w1;
     } else {
         T w1 = c2 * T(c.kax);
         T w5 = w1 * T(c.ratio);
-        w[0] = T(1) - T(4) * w1 - T(4) * w5;
+        w[0] = fmaT(T(-4), w5, fmaT(T(-4), w1, T(1)));
 #pragma unroll
         for (int i = 1; i < Q; ++i) w[i] = i <= 4 ? w1 : w5;
     }
 }
 
-// c_i . J with the lattice velocity's components (0, +-1) resolved at compile
+// c . J for the velocity (cx, cy) with components 0, +-1 resolved at compile
 // time (no multiplications by 0 or 1).
-template <typename T, int Q>
-__device__ inline T cdot(int i, T jx, T jy) {
-    const int cx = cxv<Q>(i), cy = cyv<Q>(i);
+template <typename T>
+__device__ inline T cdot(int cx, int cy, T jx, T jy) {
     const T ax = cx > 0 ? jx : -jx, ay = cy > 0 ? jy : -jy;
     return cx != 0 ? (cy != 0 ? ax + ay : ax) : (cy != 0 ? ay : T(0));
 }
@@ -176,11 +177,17 @@ __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&ou
     }
     weights<T, Q>(c2, c, w);
     T d[Q];
+    d[0] = g[0] - w[0] * rho;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
-        T cj = cdot<T, Q>(i, jx, jy);
-        T geq = fmaT(w[i], rho, i == 0 ? T(0) : kj * cj);
+    for (int i = 1; i < Q; ++i) {
+        // (w_i / c^2)(c_i . J): opposite velocities share one product
+        // (k (-a) is -(k a) exactly), taken for the one whose first nonzero
+        // component is positive
+        const int cx = cxv<Q>(i), cy = cyv<Q>(i);
+        const bool pos = cx > 0 || (cx == 0 && cy > 0);
+        const T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(c.kax) : T(c.kdg));
+        const T kc = kj * cdot<T>(pos ? cx : -cx, pos ? cy : -cy, jx, jy);
+        const T geq = fmaT(w[i], rho, pos ? kc : -kc);
         d[i] = g[i] - geq;
     }
     if (KIND == 0) {
@@ -261,9 +268,11 @@ __device__ inline void record_node(const Receivers &rc, int rb, int re, int x, c
 
 // Post-collision state of node (x, y): collision, source w_i S at the source
 // node, sponge (dedge: the node's distance to the nearest grid edge).
+// maybe_sponge: wave-uniform; false when no node of the wave's current row
+// lies in the sponge (dedge is then not looked at).
 template <typename T, int Q, int KIND>
 __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int x, int y, int dedge, double s_n,
-                                 T (&out)[Q]) {
+                                 T (&out)[Q], bool maybe_sponge = true) {
     T gs[Q], w[Q];
     collide<T, Q, KIND>(g, c2, p.coll, gs, w);
     if (y == p.src_y) {   // uniform over a row: only the source row tests x
@@ -276,9 +285,18 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
             for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
         }
     }
-    const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
+    // sponge: outside it the factor is 1 and g * 1 = g, so only nodes inside
+    // multiply (a branch, kept by the empty asm, rather than selects at
+    // every node)
+    if (maybe_sponge && dedge < p.sponge_width) {
+        asm volatile("");
+        const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
+        for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[i] = gs[i];
+    }
 }
 
 }  // namespace
