@@ -21,12 +21,11 @@ constexpr int kAdvBlock = 256;
 // that streams into the segment), then walks down the rows computing
 // h(n+1), ..., h(n+NS) from the rows above, at and below, in registers, and
 // stores each finished row.  Pulls along x come from the neighbouring lane
-// (DPP lane shifts).  The strip carries kT2Halo halo lanes on each side (NS
-// columns are needed), chosen so that strip edges fall on 64-byte
-// boundaries: measured on MI355X with copy kernels of this access pattern,
-// strips whose edges split 32/64-byte words, and waves that stream one row
-// at a time, reach only 3-4.5 TB/s, while all-rows-at-once loads with
-// aligned edges match a row-major pass (5.5-5.8 TB/s).  Halo rows and lanes
+// (DPP lane shifts).  The strip carries H halo lanes on each side (NS
+// columns are needed; see Tb).  Measured on MI355X with copy kernels of
+// this access pattern, waves that stream one row at a time reach only
+// 3-4.5 TB/s, while all-rows-at-once loads match a row-major pass
+// (5.5-5.8 TB/s with strip edges on 64-byte boundaries).  Halo rows and lanes
 // are computed redundantly and never stored; the halo's intermediate states
 // are the same arithmetic at the same nodes (rounded to the storage format),
 // so the result equals NS launches of the one-step kernel bit for bit.  Only
@@ -36,7 +35,11 @@ constexpr int kT2Halo = 4;    // halo lanes per side
 
 template <typename S> struct Tb {
     static constexpr int V = sizeof(S) == 8 ? 1 : int(8 / sizeof(S));   // 8-byte lane accesses
-    static constexpr int H = kT2Halo;
+    // FP32: two halo lanes (4 columns, enough for 4 steps; strip edges at
+    // 480 B, measured 2 % faster than four lanes at 448 B: less redundant
+    // work outweighs the unaligned edges once the kernel is not
+    // bandwidth-bound)
+    static constexpr int H = sizeof(S) == 4 ? 2 : kT2Halo;
     static constexpr int OW = (64 - 2 * H) * V;                          // owned columns per wave (448 B)
 };
 
@@ -49,6 +52,15 @@ template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_
 template <typename U>
 __device__ inline U ld_hint(const U *p, bool keep) {
     return keep ? *p : __builtin_nontemporal_load(p);
+}
+
+// Element x of a row as a wave-uniform row pointer plus an unsigned 32-bit
+// byte offset per lane, so that the access takes the scalar-base form
+// (no per-lane 64-bit address arithmetic).  x >= 0 and x * sizeof(U) < 2^32.
+template <typename U, typename E>
+__device__ inline U *at_lane(E *row, int x) {
+    return reinterpret_cast<U *>(reinterpret_cast<
+        std::conditional_t<std::is_const_v<E>, const char, char> *>(row) + (uint32_t)x * (uint32_t)sizeof(E));
 }
 
 template <bool VEC, int SEL, bool KEEP, typename S, typename T, int Q, int V>
@@ -64,7 +76,7 @@ __device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, in
         const S *r = base + i * pstride + rowoff;
         if constexpr (VEC && V > 1) {
             typedef typename LaneVec<V, S>::type vt;
-            vt t = ld_hint(reinterpret_cast<const vt *>(r + xv), KEEP);
+            vt t = ld_hint(at_lane<const vt>(r, xv), KEEP);
 #pragma unroll
             for (int j = 0; j < V; ++j) out[i][j] = T(t[j]);
         } else {
@@ -78,7 +90,7 @@ template <bool VEC, bool KEEP, typename T, int V>
 __device__ inline void load_c2row(const T *__restrict__ c2, int64_t rowoff, int xv, const int (&xw)[V], T (&out)[V]) {
     if constexpr (VEC && V > 1) {
         typedef typename LaneVec<V, T>::type vt;
-        vt t = ld_hint(reinterpret_cast<const vt *>(c2 + rowoff + xv), KEEP);
+        vt t = ld_hint(at_lane<const vt>(c2 + rowoff, xv), KEEP);
 #pragma unroll
         for (int j = 0; j < V; ++j) out[j] = t[j];
     } else {
@@ -242,9 +254,18 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     if (has_rec && lane <= y1 - y0) rowv = p.rec.row_ptr[y0 + lane];
 
     T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], L3[K][Q][V], C[K][V];
+    // wrapped row of index k: one modulo for the first, then a step with a
+    // reset at ny (consecutive rows)
+    int wr = wrapi(y0 - NS, ny);
+    int wrow[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int64_t ro = (int64_t)wrapi(y0 - NS + k, ny) * nx;
+        wrow[k] = wr;
+        wr = wr + 1 == ny ? 0 : wr + 1;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t ro = (int64_t)wrow[k] * nx;
         if (k == 0) {
             load_row2<VEC, 1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
         } else if (k == K - 1) {
@@ -267,7 +288,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
         const bool owned_row = gm >= y0 && gm < y1;
         if (st == nrun && !owned_row) return;   // the last stage computes owned rows only
         auto &A = pick4<st - 1>(L0, L1, L2, L3);
-        const int wm = wrapi(gm, ny);
+        const int wm = wrow[m];
         T g[Q][V];
         pull_row2<T, Q, V>(A[m - 1], A[m], A[m + 1], g);
         int rb = 0, re = 0;
@@ -302,7 +323,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
                             vt t;
 #pragma unroll
                             for (int j = 0; j < V; ++j) t[j] = S(po[i][j]);
-                            __builtin_nontemporal_store(t, reinterpret_cast<vt *>(r + xv));
+                            __builtin_nontemporal_store(t, at_lane<vt>(r, xv));
                         }
                     } else {
 #pragma unroll

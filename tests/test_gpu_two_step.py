@@ -38,10 +38,10 @@ def both(case, precision, spl=0, **kw):
 
 def boundary_receivers(nx, ny):
     """Receivers on the strip edges of every storage format (owned widths
-    112 for FP32, 56 for FP64, 224 for FP16 storage), on 8-row segment edges
-    and on the periodic seam."""
+    120 for FP32, 56 for FP64, 224 for FP16 storage), on 4-, 6- and 8-row
+    segment edges and on the periodic seam."""
     xs = {0, 1, nx - 1, nx - 2}
-    for w in (56, 112, 224):
+    for w in (56, 120, 224):
         for k in range(1, nx // w + 1):
             xs.update({k * w - 1, k * w, k * w + 1})
     ys = {0, 1, ny - 1, ny - 2}
@@ -79,8 +79,8 @@ def test_step_count_remainders(nsteps):
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 2), (5, 7), (56, 61), (112, 16), (113, 17),
-                                   (224, 3), (2, 300), (1029, 3), (448, 9)])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 2), (5, 7), (56, 61), (112, 16), (113, 17), (120, 5),
+                                   (121, 9), (224, 3), (2, 300), (1029, 3), (448, 9)])
 def test_two_step_shapes(precision, nx, ny):
     rho, jx, jy = inputs.random_fields(nx, ny, seed=nx * 17 + ny)
     rng = np.random.default_rng(nx * ny + 3)
