@@ -75,9 +75,10 @@ def test_graph_replays_match_eager_launches():
 
 @pytest.mark.parametrize("tick", [7, 16, 33])
 def test_two_step_batch_equals_one_step_batch(tick):
-    """Two steps per batched launch (odd ticks end with a one-step launch;
-    shots with an odd number of steps end with a single step inside a
-    two-step launch) give the bits of one step per launch."""
+    """Several steps per batched launch (ticks that are not a multiple of
+    the step count end with a shorter launch; shots whose remaining steps are
+    fewer take those inside a full launch) give the bits of one step per
+    launch."""
     sched = [(0, SHOTS[0]), (1, SHOTS[3]), (2, SHOTS[1]), (2, SHOTS[2]), (0, shot(130, 70, 151, 5))]
     a = run_batch(sched, tick=tick, steps_per_launch=1, max_shots=5)
     b = run_batch(sched, tick=tick, max_shots=5)

@@ -240,7 +240,7 @@ def test_full_size_layered_f32(q, collision, s, nsteps):
             "wavelet": wl["wavelet"], "receivers": wl["receivers"],
             "rho0": rho, "jx0": jx, "jy0": jy}
     # as the benchmark launches it: no sum-of-rho recording, so lb_step_n
-    # takes two steps per launch
+    # takes several steps per launch
     compare(case, "f32", gpu=run_gpu(case, "f32", sum_rho=False))
 
 

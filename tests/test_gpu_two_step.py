@@ -123,7 +123,7 @@ def test_chunked_calls_mix_one_and_two_step_launches():
 
 def test_sum_rho_recording_keeps_one_step_and_matches():
     """With the sum of rho recorded every step lb_step_n takes one step per
-    launch; traces and fields equal those of the two-step path."""
+    launch; traces and fields equal those of the blocked path."""
     case = layered_case(400, 36, nsteps=50)
     a = run_gpu(case, "f32", sum_rho=True)
     b = run_gpu(case, "f32", sum_rho=False)
@@ -132,7 +132,8 @@ def test_sum_rho_recording_keeps_one_step_and_matches():
 
 def test_two_step_vs_oracle_pulse_f64():
     """The 128^2 periodic Gaussian-pulse case (tau = 1, FP64) through the
-    two-step path: rho field against the oracle at the FP64 bar."""
+    blocked path (four steps per launch): rho field against the oracle at
+    the FP64 bar."""
     wl = inputs.pulse_workload()
     case = {"nx": 128, "ny": 128, "q": 5, "collision": "bgk", "tau": 1.0,
             "c2": wl["c2"], "rho0": wl["rho0"], "nsteps": wl["nsteps"],
