@@ -186,7 +186,7 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
             "misfit": float(phi.item()), "gradient_finite": finite}
 
 
-KERNEL_SOURCES = ("lb_blocked.hip", "lb_node.h", "lb_internal.h")
+KERNEL_SOURCES = ("lb_blocked.h", "lb_blocked_f32_q5.hip", "lb_node.h", "lb_internal.h")
 
 
 def kernel_source_sha256():

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbwave.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["lb_kernels.hip", "lb_blocked.hip", "lb_runtime.cpp", "lb_batch.cpp"]
+SOURCES = ["lb_blocked_f32_q5.hip", "lb_blocked_f32_q9.hip", "lb_blocked_f64_q5.hip", "lb_blocked_f64_q9.hip",
+           "lb_blocked_f16_q5.hip", "lb_kernels.hip", "lb_blocked.hip", "lb_runtime.cpp", "lb_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LBWAVE_ARCH", "gfx950")
 
@@ -42,7 +43,8 @@ def _compile(src, verbose):
 def build(verbose=False):
     """Compile every HIP source for gfx950 and link liblbwave.so."""
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    # the blocked-kernel sources are the slow ones: they start first
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), max(2, os.cpu_count() or 2))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

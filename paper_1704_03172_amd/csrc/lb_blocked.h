@@ -1,0 +1,498 @@
+// lb_blocked.h -- the temporally blocked step kernel of the linear LB scheme
+// (several time steps per launch), for single grids and for the batched
+// executor, and its templated launchers.  The per-node arithmetic is that of
+// the one-step kernel (lb_node.h), so both give the same bits.  Included by
+// one source per storage format and lattice (lb_blocked_*.hip, compiled in
+// parallel) and by the dispatcher lb_blocked.hip.  Device code only; not
+// part of the public interface.
+#pragma once
+
+#include "lb_internal.h"
+#include "lb_node.h"
+
+#include <type_traits>
+
+namespace lbw {
+namespace {
+
+// ---- NS time steps per launch ---------------------------------------------------
+// Temporal blocking: one pass reads h(n) and writes h(n+NS), so every
+// population element crosses HBM once per NS updates (NS up to 4, see
+// tn_max).  A wavefront owns a strip of columns and a
+// segment of rows: it loads the segment's rows of h(n) plus NS halo rows on
+// each side, all at once (of the outermost halo rows only the population
+// that streams into the segment), then walks down the rows computing
+// h(n+1), ..., h(n+NS) from the rows above, at and below, in registers, and
+// stores each finished row.  Pulls along x come from the neighbouring lane
+// (DPP lane shifts).  The strip carries H halo lanes on each side (NS
+// columns are needed; see Tb).  Measured on MI355X with copy kernels of
+// this access pattern, waves that stream one row at a time reach only
+// 3-4.5 TB/s, while all-rows-at-once loads match a row-major pass
+// (5.5-5.8 TB/s with strip edges on 64-byte boundaries).  Halo rows and lanes
+// are computed redundantly and never stored; the halo's intermediate states
+// are the same arithmetic at the same nodes (rounded to the storage format),
+// so the result equals NS launches of the one-step kernel bit for bit.  Only
+// rows and columns the wave owns are recorded.
+constexpr int kT2Block = 256;
+constexpr int kT2Halo = 4;    // halo lanes per side
+
+template <typename S> struct Tb {
+    static constexpr int V = sizeof(S) == 8 ? 1 : int(8 / sizeof(S));   // 8-byte lane accesses
+    // FP32: two halo lanes (4 columns, enough for 4 steps; strip edges at
+    // 480 B, measured 2 % faster than four lanes at 448 B: less redundant
+    // work outweighs the unaligned edges once the kernel is not
+    // bandwidth-bound)
+    static constexpr int H = sizeof(S) == 4 ? 2 : kT2Halo;
+    static constexpr int OW = (64 - 2 * H) * V;                          // owned columns per wave (448 B)
+};
+
+template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_vector_type(V), aligned(sizeof(S)))); };
+
+// One row (all populations) of the lane's V columns, converted to T.  VEC:
+// one vector access at the lane's wrapped first column xv (the lane's
+// columns are contiguous after the wrap when nx is a multiple of V);
+// otherwise element accesses at the wrapped columns xw.
+template <typename U>
+__device__ inline U ld_hint(const U *p, bool keep) {
+    return keep ? *p : __builtin_nontemporal_load(p);
+}
+
+// Element x of a row as a wave-uniform row pointer plus an unsigned 32-bit
+// byte offset per lane, so that the access takes the scalar-base form
+// (no per-lane 64-bit address arithmetic).  x >= 0 and x * sizeof(U) < 2^32.
+template <typename U, typename E>
+__device__ inline U *at_lane(E *row, int x) {
+    return reinterpret_cast<U *>(reinterpret_cast<
+        std::conditional_t<std::is_const_v<E>, const char, char> *>(row) + (uint32_t)x * (uint32_t)sizeof(E));
+}
+
+template <bool VEC, int SEL, bool KEEP, typename S, typename T, int Q, int V>
+__device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, int64_t rowoff, int xv,
+                                 const int (&xw)[V], T (&out)[Q][V]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if ((SEL > 0 && cyv<Q>(i) <= 0) || (SEL < 0 && cyv<Q>(i) >= 0)) {   // not needed from this row
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(0);
+            continue;
+        }
+        const S *r = base + i * pstride + rowoff;
+        if constexpr (VEC && V > 1) {
+            typedef typename LaneVec<V, S>::type vt;
+            vt t = ld_hint(at_lane<const vt>(r, xv), KEEP);
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(t[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) out[i][j] = T(ld_hint(r + xw[j], KEEP));
+        }
+    }
+}
+
+template <bool VEC, bool KEEP, typename T, int V>
+__device__ inline void load_c2row(const T *__restrict__ c2, int64_t rowoff, int xv, const int (&xw)[V], T (&out)[V]) {
+    if constexpr (VEC && V > 1) {
+        typedef typename LaneVec<V, T>::type vt;
+        vt t = ld_hint(at_lane<const vt>(c2 + rowoff, xv), KEEP);
+#pragma unroll
+        for (int j = 0; j < V; ++j) out[j] = t[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) out[j] = ld_hint(c2 + rowoff + xw[j], KEEP);
+    }
+}
+
+// Whole-wave lane shifts by one lane (DPP wave_shr:1 / wave_shl:1, GFX9
+// encodings 0x138 / 0x130): from_lower(v) in lane l is v of lane l - 1,
+// from_upper(v) is v of lane l + 1 (the end lanes keep their own value;
+// they are halo lanes).
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename T>
+__device__ inline T dpp_shift(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+template <typename T> __device__ inline T from_lower(T v) { return dpp_shift<0x138>(v); }
+template <typename T> __device__ inline T from_upper(T v) { return dpp_shift<0x130>(v); }
+
+// Pulled (pre-collision) state of one row from the rows above (U, y - 1),
+// at (C) and below (D, y + 1) it: g_i(x) = h_i(x - c_i).
+template <typename T, int Q, int V>
+__device__ inline void pull_row2(const T (&U)[Q][V], const T (&C)[Q][V], const T (&D)[Q][V], T (&g)[Q][V]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T r[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) r[j] = cyv<Q>(i) > 0 ? U[i][j] : cyv<Q>(i) < 0 ? D[i][j] : C[i][j];
+        if (cxv<Q>(i) > 0) {          // from x - 1
+            const T l = from_lower(r[V - 1]);
+#pragma unroll
+            for (int j = V - 1; j > 0; --j) g[i][j] = r[j - 1];
+            g[i][0] = l;
+        } else if (cxv<Q>(i) < 0) {   // from x + 1
+            const T rr = from_upper(r[0]);
+#pragma unroll
+            for (int j = 0; j < V - 1; ++j) g[i][j] = r[j + 1];
+            g[i][V - 1] = rr;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) g[i][j] = r[j];
+        }
+    }
+}
+
+// Blocks are dealt to the 8 XCDs round-robin (block b on XCD b mod 8);
+// renumbered, each XCD takes a contiguous range of strips and segments, whose
+// shared halo rows then meet in that XCD's L2.
+__device__ inline int xcd_block() {
+    const int nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, b = blockIdx.x, x8 = b % 8;
+    return x8 * q8 + min(x8, r8) + b / 8;
+}
+
+// f(integral_constant<int, i>) for i = B .. E-1, unrolled at compile time (a
+// loop this large is beyond the unroller's size limit, and runtime row
+// indices would put the row arrays in scratch memory).
+template <int B, typename F, int... I>
+__device__ inline void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, B + I>{}), ...);
+}
+template <int B, int E, typename F>
+__device__ inline void static_for(F &&f) {
+    static_for_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+
+// One of four arrays chosen at compile time (separate arrays per stage stay
+// in registers; one array of all stages would be too large to promote).
+template <int I, typename A>
+__device__ inline A &pick4(A &a0, A &a1, A &a2, A &a3) {
+    if constexpr (I == 0) return a0;
+    else if constexpr (I == 1) return a1;
+    else if constexpr (I == 2) return a2;
+    else return a3;
+}
+
+// Steps per launch the blocked kernel offers for a configuration: the most
+// whose per-stage row state still fits in registers without scratch memory
+// (measured at 4096^2 on MI355X, each count was faster than the one below
+// it).  1: not offered (D2Q9 with FP16 storage, whose 4-column lanes would
+// hold their rows in scratch).
+template <typename S, int Q, int KIND>
+constexpr int tn_max() {
+    if constexpr (sizeof(S) == 2) return Q == 5 ? 2 : 1;
+    else if constexpr (Q == 9 && sizeof(S) == 4) return KIND == 1 ? 2 : 3;
+    else return 4;
+}
+
+// Rows per segment for NS steps: the segment rows plus NS halo rows on each
+// side sit in registers (K = rows + 2 NS rows per stage), so more steps and
+// larger per-row states (D2Q9, FP16 storage with 4 columns per lane) take
+// shorter segments.
+template <typename S, int Q, int NS>
+constexpr int tn_rows() {
+    if constexpr (NS == 2 && Q == 5 && sizeof(S) == 4) return 8;
+    else if constexpr (NS == 3 && Q == 5) return 6;
+    else return 4;
+}
+
+// Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch.  The
+// wave takes nrun <= NS steps (FULL: NS, known at compile time): stage s
+// (1..nrun) computes h(n+s) from h(n+s-1); the state of stage nrun is
+// stored.
+template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL>
+__device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
+    using T = typename Tr<S>::T;
+    constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS>(), K = LY + 2 * NS;
+    static_assert(H * V >= NS, "the strip halo must cover one column per step");
+    const int nx = p.nx, ny = p.ny;
+    const int nstrip = (nx + OW - 1) / OW;
+    const int nseg = (ny + LY - 1) / LY;
+    if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
+    const int lane = threadIdx.x & 63;
+    const int sx = wave % nstrip, sy = wave / nstrip;
+    const int xl = sx * OW - H * V + lane * V;   // first column of this lane
+    const int y0 = sy * LY, y1 = min(y0 + LY, ny);
+    int xw[V];
+    bool own[V];
+    const bool own_lane = lane >= H && lane < 64 - H;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        xw[j] = wrapi(xl + j, nx);
+        own[j] = own_lane && xl + j < nx;
+    }
+    const int nrun = FULL ? NS : nrun_arg;
+    const int xv = xw[0];   // VEC: the lane's columns are xv .. xv + V - 1
+    // whether any column of the strip (halo lanes included, before the wrap)
+    // lies within the sponge width of a side edge: else the sponge depends
+    // on the row alone
+    const int L = p.sponge_width;
+    const bool strip_sponge = sx * OW - H * V < L || sx * OW - H * V + 64 * V - 1 >= nx - L;
+    int dxw[V];             // distance of each column to the nearest side edge
+#pragma unroll
+    for (int j = 0; j < V; ++j) dxw[j] = min(xw[j], nx - 1 - xw[j]);
+    const S *src = reinterpret_cast<const S *>(p.src);
+    S *dst = reinterpret_cast<S *>(p.dst);
+    const T *c2 = reinterpret_cast<const T *>(p.c2);
+    const double sn[4] = {p.s_n, p.s_n2, p.s_n3, p.s_n4};
+
+    // L0[k]: row y0 - NS + k (wrapped) of h(n), all rows loaded at once;
+    // L1[k], L2[k]: the same row of h(n+1), h(n+2).  Rows that the neighbouring segments
+    // also read (the NS halo rows and the NS edge rows on each side) are
+    // loaded with the ordinary cache policy, so that the segment loaded
+    // second finds them in L2; the others stream (nontemporal).  Of the
+    // outermost rows only the populations that stream into the segment are
+    // needed.
+    // this segment's slice of the receiver row table: lane k holds
+    // row_ptr[y0 + k], read back per row with readlane (loaded before the
+    // rows so that its wait does not hold the arithmetic behind them)
+    const bool has_rec = p.rec.row_ptr != nullptr;
+    int rowv = 0;
+    if (has_rec && lane <= y1 - y0) rowv = p.rec.row_ptr[y0 + lane];
+
+    T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], L3[K][Q][V], C[K][V];
+    // wrapped row of index k: one modulo for the first, then a step with a
+    // reset at ny (consecutive rows)
+    int wr = wrapi(y0 - NS, ny);
+    int wrow[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        wrow[k] = wr;
+        wr = wr + 1 == ny ? 0 : wr + 1;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t ro = (int64_t)wrow[k] * nx;
+        if (k == 0) {
+            load_row2<VEC, 1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
+        } else if (k == K - 1) {
+            load_row2<VEC, -1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
+        } else if (k < 2 * NS || k >= K - 2 * NS) {
+            load_row2<VEC, 0, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
+            load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
+        } else {
+            load_row2<VEC, 0, false, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
+            load_c2row<VEC, false, T, V>(c2, ro, xv, xw, C[k]);
+        }
+    }
+
+    // stage st (1..NS) at row m: h(n+st) from rows m-1, m, m+1 of h(n+st-1)
+    auto stage = [&](auto stc, auto mc) __attribute__((always_inline)) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int m = decltype(mc)::value;
+        if (st > nrun) return;
+        const int gm = y0 - NS + m;   // unwrapped row
+        const bool owned_row = gm >= y0 && gm < y1;
+        if (st == nrun && !owned_row) return;   // the last stage computes owned rows only
+        auto &A = pick4<st - 1>(L0, L1, L2, L3);
+        const int wm = wrow[m];
+        T g[Q][V];
+        pull_row2<T, Q, V>(A[m - 1], A[m], A[m + 1], g);
+        int rb = 0, re = 0;
+        if (has_rec && owned_row) {
+            rb = __builtin_amdgcn_readlane(rowv, m - NS);
+            re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
+        }
+        Receivers rc = p.rec;
+        rc.col = p.rec.col + st - 1;
+        T po[Q][V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            T gj[Q], pj[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+            if (rb < re && own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, C[m][j]);
+            post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), sn[st - 1], pj,
+                                  strip_sponge || min(wm, ny - 1 - wm) < L);
+            // rounded to the storage format, as a stored h(n+st) would be
+#pragma unroll
+            for (int i = 0; i < Q; ++i) po[i][j] = T(to_store<S>(pj[i]));
+        }
+        if (st == nrun) {
+            if (owned_row) {   // the result of this launch
+                const int64_t ro = (int64_t)gm * nx;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    S *r = dst + i * p.pstride + ro;
+                    if constexpr (VEC && V > 1) {
+                        if (own[0]) {   // nx is a multiple of V: an owned lane owns all its columns
+                            typedef typename LaneVec<V, S>::type vt;
+                            vt t;
+#pragma unroll
+                            for (int j = 0; j < V; ++j) t[j] = S(po[i][j]);
+                            __builtin_nontemporal_store(t, at_lane<vt>(r, xv));
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < V; ++j)
+                            if (own[j]) __builtin_nontemporal_store(S(po[i][j]), r + xw[j]);
+                    }
+                }
+            }
+        } else if constexpr (st < NS) {
+            auto &B = pick4<st>(L0, L1, L2, L3);
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int j = 0; j < V; ++j) B[m][i][j] = po[i][j];
+        }
+    };
+    // walk down the rows: at index k, stage st computes row m = k - st (its
+    // three source rows of stage st-1 are then complete)
+    static_for<2, K>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k - 1 >= 1 && k - 1 <= K - 2)
+            stage(std::integral_constant<int, 1>{}, std::integral_constant<int, k - 1>{});
+        if constexpr (NS >= 2 && k - 2 >= 2 && k - 2 <= K - 3)
+            stage(std::integral_constant<int, 2>{}, std::integral_constant<int, k - 2>{});
+        if constexpr (NS >= 3 && k - 3 >= 3 && k - 3 <= K - 4)
+            stage(std::integral_constant<int, 3>{}, std::integral_constant<int, k - 3>{});
+        if constexpr (NS >= 4 && k - 4 >= 4 && k - 4 <= K - 5)
+            stage(std::integral_constant<int, 4>{}, std::integral_constant<int, k - 4>{});
+    });
+}
+
+template <typename S, int Q, int KIND, bool VEC, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
+    // wave-uniform (so that the row and loop arithmetic is scalar)
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    stepn_wave<S, Q, KIND, VEC, NS, true>(p, xcd_block() * (kT2Block / 64) + wib, NS);
+}
+
+// Up to NS steps of every active shot in one launch (a shot takes
+// min(NS, bp.max_run, steps left)): wave w belongs to the active shot a with
+// wprefix[a] <= w < wprefix[a+1] (waves of nstrip x nseg per shot).
+template <typename S, int Q, int KIND, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn_batch(BatchParams bp) {
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
+    if (w >= bp.wprefix[bp.nact]) return;
+    int lo = 0, hi = bp.nact - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bp.wprefix[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int slot = bp.order[lo];
+    const ShotState ss = bp.state[slot];
+    if (!ss.active || ss.t >= ss.t_end) return;
+    const ShotEntry &e = bp.table[slot];
+    StepParams p;
+    p.src = ss.cur ? e.pop1 : e.pop0;
+    p.dst = ss.cur ? e.pop0 : e.pop1;
+    p.c2 = e.c2;
+    p.nx = e.nx;
+    p.ny = e.ny;
+    p.pstride = e.pstride;
+    p.q = Q;
+    p.coll = bp.coll;
+    p.sponge_width = e.sponge_width;
+    p.sponge_smax = e.sponge_smax;
+    p.src_x = e.src_x;
+    p.src_y = e.src_y;
+    const int64_t tn = ss.t + 1;
+    p.s_n = tn < e.wavelet_len ? e.wavelet[tn] : 0.0;
+    p.s_n2 = tn + 1 < e.wavelet_len ? e.wavelet[tn + 1] : 0.0;
+    p.s_n3 = tn + 2 < e.wavelet_len ? e.wavelet[tn + 2] : 0.0;
+    p.s_n4 = tn + 3 < e.wavelet_len ? e.wavelet[tn + 3] : 0.0;
+    p.rec = e.rec;
+    p.rec.col = tn;
+    const int nrun = (int)min<int64_t>(min(NS, bp.max_run), ss.t_end - ss.t);
+    const int lw = int(w - bp.wprefix[lo]);
+    // a shot taking all NS steps with contiguous lane columns (the common
+    // case) runs the body with the step count fixed at compile time; the
+    // rest (a shot's last launch, odd widths) the general one
+    if (nrun == NS && e.nx % Tb<S>::V == 0) stepn_wave<S, Q, KIND, true, NS, true>(p, lw, NS);
+    else stepn_wave<S, Q, KIND, false, NS, false>(p, lw, nrun);
+}
+
+// f(integral_constant<int, ns>()) for 2 <= ns <= the largest tn_max<S, Q, KIND>
+// over both collision kinds (else hipErrorInvalidValue); only those step
+// counts are instantiated.
+template <typename S, int Q, typename F>
+hipError_t by_steps(int ns, F &&f) {
+    constexpr int m = tn_max<S, Q, 0>() > tn_max<S, Q, 1>() ? tn_max<S, Q, 0>() : tn_max<S, Q, 1>();
+    if constexpr (m >= 4) if (ns == 4) return f(std::integral_constant<int, 4>());
+    if constexpr (m >= 3) if (ns == 3) return f(std::integral_constant<int, 3>());
+    if constexpr (m >= 2) if (ns == 2) return f(std::integral_constant<int, 2>());
+    return hipErrorInvalidValue;
+}
+
+template <typename S, int Q>
+int64_t waves_of(int ns, int32_t nx, int32_t ny) {
+    int ly = 1;
+    by_steps<S, Q>(ns, [&](auto nc) { ly = tn_rows<S, Q, decltype(nc)::value>(); return hipSuccess; });
+    return (int64_t)((nx + Tb<S>::OW - 1) / Tb<S>::OW) * ((ny + ly - 1) / ly);
+}
+
+// The single-grid NS-step launch for storage S and lattice Q.
+template <typename S, int Q>
+hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
+    const dim3 grid((unsigned)((waves_of<S, Q>(ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
+    // vector accesses need every lane's columns contiguous after the wrap
+    const bool vec = p.nx % Tb<S>::V == 0;
+    const int kind = step_kind(p.coll);
+    return by_steps<S, Q>(ns, [&](auto nc) {
+        constexpr int NS = decltype(nc)::value;
+        auto launch = [&](auto kc) {
+            constexpr int KK = decltype(kc)::value;
+            if constexpr (NS <= tn_max<S, Q, KK>()) {
+                if (vec) hipLaunchKernelGGL((k_stepn<S, Q, KK, true, NS>), grid, dim3(kT2Block), 0, s, p);
+                else hipLaunchKernelGGL((k_stepn<S, Q, KK, false, NS>), grid, dim3(kT2Block), 0, s, p);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        };
+        return kind == 1 ? launch(std::integral_constant<int, 1>())
+             : kind == 2 ? launch(std::integral_constant<int, 2>()) : launch(std::integral_constant<int, 0>());
+    });
+}
+
+// The batched NS-step launch for storage S and lattice Q.
+template <typename S, int Q>
+hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s) {
+    const dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const int kind = step_kind(bp.coll);
+    return by_steps<S, Q>(ns, [&](auto nc) {
+        constexpr int NS = decltype(nc)::value;
+        auto launch = [&](auto kc) {
+            constexpr int KK = decltype(kc)::value;
+            if constexpr (NS <= tn_max<S, Q, KK>()) {
+                hipLaunchKernelGGL((k_stepn_batch<S, Q, KK, NS>), grid, dim3(kT2Block), 0, s, bp);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        };
+        return kind == 1 ? launch(std::integral_constant<int, 1>())
+             : kind == 2 ? launch(std::integral_constant<int, 2>()) : launch(std::integral_constant<int, 0>());
+    });
+}
+
+}  // namespace
+
+// One source per storage format and lattice instantiates the kernels with
+// LBW_BLOCKED_UNIT; lb_blocked.hip validates and dispatches to them.
+#define LBW_BLOCKED_UNIT(SS, QQ, NAME)                                                              \
+    hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s) {                    \
+        return stepn_launch<SS, QQ>(p, ns, s);                                                      \
+    }                                                                                               \
+    hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s) { \
+        return stepn_batch_launch<SS, QQ>(bp, ns, nwaves, s);                                       \
+    }
+
+#define LBW_BLOCKED_DECL(NAME)                                                                      \
+    hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s);                     \
+    hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s);
+LBW_BLOCKED_DECL(f32_q5)
+LBW_BLOCKED_DECL(f32_q9)
+LBW_BLOCKED_DECL(f64_q5)
+LBW_BLOCKED_DECL(f64_q9)
+LBW_BLOCKED_DECL(f16_q5)
+#undef LBW_BLOCKED_DECL
+
+}  // namespace lbw

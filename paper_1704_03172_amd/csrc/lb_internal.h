@@ -35,6 +35,11 @@ struct Collision {
     double ratio = 0.0;                // D2Q9 w5 / w1
 };
 
+// Collision kind the forward kernels are instantiated for: 0 BGK, 1 MRT,
+// 2 BGK with omega = 2 (tau = 1/2), whose collision is written as
+// 2 g^eq - g.  The adjoint keeps Collision::kind.
+inline int step_kind(const Collision &c) { return c.kind == 1 ? 1 : (c.omega == 2.0 ? 2 : 0); }
+
 // Interface geometry of a factor-2 refinement patch (coarse units).
 struct PatchGeom {
     int32_t X0 = 0, Y0 = 0;            // fine node (0, 0) at coarse (X0, Y0)

@@ -23,7 +23,7 @@
 // This one-step kernel serves single steps (the last of a call, sum-of-rho
 // recording, checkpoint boundaries), the refinement patch, whose interface
 // work is fused into it, and the adjoint's forward recompute; runs of steps
-// go to the temporally blocked kernel of lb_blocked.hip.  Both take their per-node
+// go to the temporally blocked kernel of lb_blocked.h.  Both take their per-node
 // arithmetic from lb_node.h.
 #include "lb_internal.h"
 #include "lb_node.h"
@@ -728,7 +728,7 @@ template <typename S>
 hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
     const int V = vwidth<S>(pull);
     dim3 grid((unsigned)(((int64_t)p0.nx + (int64_t)V * kStepBlock - 1) / ((int64_t)V * kStepBlock)), (unsigned)p0.ny);
-    const int kind = p0.coll.kind;
+    const int kind = step_kind(p0.coll);
     StepParams p = p0;
     p.pre_rows = 0;
     if (p0.prolong_on) {
@@ -738,9 +738,9 @@ hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
             p.pre_rows = rows;
             grid.y += (unsigned)rows;
         } else {   // a launch of its own first
-            const bool mrt = kind == 1;
             dim3 pg(blocks_for(p0.iface.g.nring));
-            if (mrt) hipLaunchKernelGGL((k_prolong_pair<S, 1>), pg, dim3(kBlock), 0, s, p0.iface);
+            if (kind == 1) hipLaunchKernelGGL((k_prolong_pair<S, 1>), pg, dim3(kBlock), 0, s, p0.iface);
+            else if (kind == 2) hipLaunchKernelGGL((k_prolong_pair<S, 2>), pg, dim3(kBlock), 0, s, p0.iface);
             else hipLaunchKernelGGL((k_prolong_pair<S, 0>), pg, dim3(kBlock), 0, s, p0.iface);
         }
     }
@@ -748,9 +748,11 @@ hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
     hipLaunchKernelGGL((k_step<S, QQ, KK, PP>), grid, dim3(kStepBlock), 0, s, p)
     if (p.q == 5) {
         if (kind == 0) { if (pull) LBW_LAUNCH(5, 0, true); else LBW_LAUNCH(5, 0, false); }
+        else if (kind == 2) { if (pull) LBW_LAUNCH(5, 2, true); else LBW_LAUNCH(5, 2, false); }
         else { if (pull) LBW_LAUNCH(5, 1, true); else LBW_LAUNCH(5, 1, false); }
     } else {
         if (kind == 0) { if (pull) LBW_LAUNCH(9, 0, true); else LBW_LAUNCH(9, 0, false); }
+        else if (kind == 2) { if (pull) LBW_LAUNCH(9, 2, true); else LBW_LAUNCH(9, 2, false); }
         else { if (pull) LBW_LAUNCH(9, 1, true); else LBW_LAUNCH(9, 1, false); }
     }
 #undef LBW_LAUNCH
@@ -783,10 +785,11 @@ int step_tile_nodes(int storage) { return step_vwidth(storage) * kStepBlock; }
 hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s) {
     if (nblocks <= 0 || bp.nact <= 0) return hipSuccess;
     dim3 grid((unsigned)nblocks);
-    const bool mrt = bp.coll.kind == 1;
+    const int kind = step_kind(bp.coll);
 #define LBW_B(SS, QQ)                                                                              \
     do {                                                                                           \
-        if (mrt) hipLaunchKernelGGL((k_step_batch<SS, QQ, 1>), grid, dim3(kStepBlock), 0, s, bp);  \
+        if (kind == 1) hipLaunchKernelGGL((k_step_batch<SS, QQ, 1>), grid, dim3(kStepBlock), 0, s, bp); \
+        else if (kind == 2) hipLaunchKernelGGL((k_step_batch<SS, QQ, 2>), grid, dim3(kStepBlock), 0, s, bp); \
         else hipLaunchKernelGGL((k_step_batch<SS, QQ, 0>), grid, dim3(kStepBlock), 0, s, bp);      \
     } while (0)
     if (storage == ST_F32) { if (q == 5) LBW_B(float, 5); else LBW_B(float, 9); }
@@ -887,15 +890,18 @@ hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+#define LBW_IFACE_KIND(KERNEL, SS)                                                                 \
+    do {                                                                                           \
+        if (kind == 1) hipLaunchKernelGGL((KERNEL<SS, 1>), grid, dim3(kBlock), 0, s, p);           \
+        else if (kind == 2) hipLaunchKernelGGL((KERNEL<SS, 2>), grid, dim3(kBlock), 0, s, p);      \
+        else hipLaunchKernelGGL((KERNEL<SS, 0>), grid, dim3(kBlock), 0, s, p);                     \
+    } while (0)
 #define LBW_IFACE(KERNEL, N)                                                                       \
     dim3 grid(blocks_for(N));                                                                      \
-    const bool mrt = p.coll.kind == 1;                                                             \
-    if (storage == ST_F32) { if (mrt) hipLaunchKernelGGL((KERNEL<float, 1>), grid, dim3(kBlock), 0, s, p); \
-                             else hipLaunchKernelGGL((KERNEL<float, 0>), grid, dim3(kBlock), 0, s, p); }   \
-    else if (storage == ST_F64) { if (mrt) hipLaunchKernelGGL((KERNEL<double, 1>), grid, dim3(kBlock), 0, s, p); \
-                                  else hipLaunchKernelGGL((KERNEL<double, 0>), grid, dim3(kBlock), 0, s, p); } \
-    else { if (mrt) hipLaunchKernelGGL((KERNEL<_Float16, 1>), grid, dim3(kBlock), 0, s, p);         \
-           else hipLaunchKernelGGL((KERNEL<_Float16, 0>), grid, dim3(kBlock), 0, s, p); }           \
+    const int kind = step_kind(p.coll);                                                            \
+    if (storage == ST_F32) LBW_IFACE_KIND(KERNEL, float);                                          \
+    else if (storage == ST_F64) LBW_IFACE_KIND(KERNEL, double);                                    \
+    else LBW_IFACE_KIND(KERNEL, _Float16);                                                         \
     return hipGetLastError();
 
 hipError_t launch_prolong(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong, p.g.nring) }

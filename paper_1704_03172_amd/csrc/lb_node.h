@@ -152,8 +152,10 @@ __device__ inline T cdot(int cx, int cy, T jx, T jy) {
 }
 
 // Collision of one node: out = g - C (g - g^eq) with the linear equilibrium
-// g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I, MRT
-// C = M^-1 S M applied through the non-conserved moments only.
+// g^eq_i = w_i rho + (w_i / c^2)(c_i . J); BGK C = omega I (KIND 0), MRT
+// C = M^-1 S M applied through the non-conserved moments only (KIND 1).
+// KIND 2 is BGK at omega = 2 (tau = 1/2, the non-dissipative case), where
+// g - 2 (g - g^eq) is 2 g^eq - g: one rounding less and fewer operations.
 template <typename T, int Q, int KIND>
 __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&out)[Q], T (&w)[Q]) {
     // moments, each sum started from its first term (0 + x is not x for
@@ -176,6 +178,26 @@ __device__ inline void collide(const T (&g)[Q], T c2, const Collision &c, T (&ou
         }
     }
     weights<T, Q>(c2, c, w);
+    if constexpr (KIND == 2) {
+        if constexpr (Q == 5) {
+            // D2Q5: 2 w_i = c^2 and 2 (w_i / c^2)(c_i . J) = c_i . J for the
+            // movers (both exact), 2 w_0 = 2 - 4 c^2
+            out[0] = fmaT(fmaT(T(-4), c2, T(2)), rho, -g[0]);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) out[i] = fmaT(c2, rho, cdot<T>(cxv<Q>(i), cyv<Q>(i), jx, jy)) - g[i];
+        } else {
+            out[0] = fmaT(T(2), w[0] * rho, -g[0]);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int cx = cxv<Q>(i), cy = cyv<Q>(i);
+                const bool pos = cx > 0 || (cx == 0 && cy > 0);
+                const T kj = i <= 4 ? T(c.kax) : T(c.kdg);
+                const T kc = kj * cdot<T>(pos ? cx : -cx, pos ? cy : -cy, jx, jy);
+                out[i] = fmaT(T(2), fmaT(w[i], rho, pos ? kc : -kc), -g[i]);
+            }
+        }
+        return;
+    }
     T d[Q];
     d[0] = g[0] - w[0] * rho;
 #pragma unroll
