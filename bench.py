@@ -393,7 +393,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-                     "kernel": "k_stepn<float,5,BGK,%d> (%d steps per launch)" % (nsl, nsl),
+                     "kernel": "k_stepn<float,5,BGK tau=1/2,%d> (%d steps per launch)" % (nsl, nsl),
                      "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": nsl * N,
                      "avg_kernel_us": round(kern_s * 1e6, 3)},
         # the bytes a one-step-per-launch path would move per step (44 per

@@ -69,6 +69,19 @@ def test_two_step_equals_one_step(precision, q, collision, s, spl):
         compare(case, precision, gpu=two)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("q", [5, 9])
+def test_general_bgk_equals_one_step(precision, q):
+    """BGK with tau != 1/2 (the general collision g - omega (g - g^eq); at
+    tau = 1/2 every kernel writes it as 2 g^eq - g instead): the blocked
+    kernel gives the bits of one step per launch and meets the oracle bars."""
+    case = layered_case(400, 37, q=q, collision="bgk", tau=0.8, nsteps=45)
+    case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(400, 37)])
+    two = both(case, precision)
+    if precision != "f16s":
+        compare(case, precision, gpu=two)
+
+
 @pytest.mark.parametrize("nsteps", [2, 3, 4, 5, 6, 7, 8, 9, 30, 31, 32, 33])
 def test_step_count_remainders(nsteps):
     """Every remainder of the step count modulo the four steps per launch
