@@ -193,14 +193,27 @@ constexpr int tn_max() {
 
 // Rows per segment for NS steps: the segment rows plus NS halo rows on each
 // side sit in registers (K = rows + 2 NS rows per stage), so more steps and
-// larger per-row states (D2Q9, FP16 storage with 4 columns per lane) take
-// shorter segments.
-template <typename S, int Q, int NS>
+// larger per-row states (D2Q9, FP16 storage with 4 columns per lane, the MRT
+// collision) take shorter segments.  Four steps of D2Q5 load their rows a
+// prefetch distance ahead of the walk (tn_prefetch), which leaves room for
+// taller segments (measured at 4096^2: 6 rows 8-9 % faster than 4).
+#ifndef LBW_LY4_BGK
+#define LBW_LY4_BGK 6
+#endif
+#ifndef LBW_LY4_MRT
+#define LBW_LY4_MRT 5
+#endif
+template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
-    if constexpr (NS == 2 && Q == 5 && sizeof(S) == 4) return 8;
+    if constexpr (NS == 4 && Q == 5) return sizeof(S) == 8 ? 6 : KIND == 1 ? LBW_LY4_MRT : LBW_LY4_BGK;
+    else if constexpr (NS == 2 && Q == 5 && sizeof(S) == 4) return 8;
     else if constexpr (NS == 3 && Q == 5) return 6;
     else return 4;
 }
+
+// Rows the walk keeps loads ahead (0: all rows of the segment at once).
+template <int Q, int NS>
+constexpr int tn_prefetch() { return NS == 4 && Q == 5 ? 6 : 0; }
 
 // Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch.  The
 // wave takes nrun <= NS steps (FULL: NS, known at compile time): stage s
@@ -209,7 +222,8 @@ constexpr int tn_rows() {
 template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL>
 __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     using T = typename Tr<S>::T;
-    constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS>(), K = LY + 2 * NS;
+    constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS, KIND>(), K = LY + 2 * NS;
+    constexpr int PD = tn_prefetch<Q, NS>();
     static_assert(H * V >= NS, "the strip halo must cover one column per step");
     const int nx = p.nx, ny = p.ny;
     const int nstrip = (nx + OW - 1) / OW;
@@ -266,21 +280,25 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
         wrow[k] = wr;
         wr = wr + 1 == ny ? 0 : wr + 1;
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
+    // rows loaded up front: all, or (PD > 0) the first PD + 2, the rest PD
+    // rows ahead of the walk (row r is first needed at walk index r)
+    constexpr int K0 = (PD > 0 && PD + 2 < K) ? PD + 2 : K;
+    auto load_k = [&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
         const int64_t ro = (int64_t)wrow[k] * nx;
-        if (k == 0) {
+        if constexpr (k == 0) {
             load_row2<VEC, 1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
-        } else if (k == K - 1) {
+        } else if constexpr (k == K - 1) {
             load_row2<VEC, -1, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
-        } else if (k < 2 * NS || k >= K - 2 * NS) {
+        } else if constexpr (k < 2 * NS || k >= K - 2 * NS) {
             load_row2<VEC, 0, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
             load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
         } else {
             load_row2<VEC, 0, false, S, T, Q, V>(src, p.pstride, ro, xv, xw, L0[k]);
             load_c2row<VEC, false, T, V>(c2, ro, xv, xw, C[k]);
         }
-    }
+    };
+    static_for<0, K0>(load_k);
 
     // stage st (1..NS) at row m: h(n+st) from rows m-1, m, m+1 of h(n+st-1)
     auto stage = [&](auto stc, auto mc) __attribute__((always_inline)) {
@@ -347,6 +365,7 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     // three source rows of stage st-1 are then complete)
     static_for<2, K>([&](auto kc) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value;
+        if constexpr (K0 < K && k + PD < K && k + PD >= K0) load_k(std::integral_constant<int, k + PD>{});
         if constexpr (k - 1 >= 1 && k - 1 <= K - 2)
             stage(std::integral_constant<int, 1>{}, std::integral_constant<int, k - 1>{});
         if constexpr (NS >= 2 && k - 2 >= 2 && k - 2 <= K - 3)
@@ -424,16 +443,20 @@ hipError_t by_steps(int ns, F &&f) {
 }
 
 template <typename S, int Q>
-int64_t waves_of(int ns, int32_t nx, int32_t ny) {
+int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
     int ly = 1;
-    by_steps<S, Q>(ns, [&](auto nc) { ly = tn_rows<S, Q, decltype(nc)::value>(); return hipSuccess; });
+    by_steps<S, Q>(ns, [&](auto nc) {
+        constexpr int NS = decltype(nc)::value;
+        ly = kind == 1 ? tn_rows<S, Q, NS, 1>() : tn_rows<S, Q, NS, 0>();
+        return hipSuccess;
+    });
     return (int64_t)((nx + Tb<S>::OW - 1) / Tb<S>::OW) * ((ny + ly - 1) / ly);
 }
 
 // The single-grid NS-step launch for storage S and lattice Q.
 template <typename S, int Q>
 hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
-    const dim3 grid((unsigned)((waves_of<S, Q>(ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const dim3 grid((unsigned)((waves_of<S, Q>(p.coll.kind, ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
     // vector accesses need every lane's columns contiguous after the wrap
     const bool vec = p.nx % Tb<S>::V == 0;
     const int kind = step_kind(p.coll);

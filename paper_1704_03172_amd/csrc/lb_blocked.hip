@@ -42,9 +42,9 @@ int stepn_max(int storage, int q, int kind) {
     });
 }
 
-int64_t stepn_waves(int storage, int q, int ns, int32_t nx, int32_t ny) {
+int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny) {
     return by_config(storage, q, [&](auto sv, auto qc) {
-        return waves_of<decltype(sv), decltype(qc)::value>(ns, nx, ny);
+        return waves_of<decltype(sv), decltype(qc)::value>(kind, ns, nx, ny);
     });
 }
 
