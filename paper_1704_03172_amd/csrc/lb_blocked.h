@@ -194,26 +194,29 @@ constexpr int tn_max() {
 // Rows per segment for NS steps: the segment rows plus NS halo rows on each
 // side sit in registers (K = rows + 2 NS rows per stage), so more steps and
 // larger per-row states (D2Q9, FP16 storage with 4 columns per lane, the MRT
-// collision) take shorter segments.  Four steps of D2Q5 load their rows a
-// prefetch distance ahead of the walk (tn_prefetch), which leaves room for
-// taller segments (measured at 4096^2: 6 rows 8-9 % faster than 4).
-#ifndef LBW_LY4_BGK
-#define LBW_LY4_BGK 6
-#endif
-#ifndef LBW_LY4_MRT
-#define LBW_LY4_MRT 5
-#endif
+// collision) take shorter segments.  The BGK kernels of four-step D2Q5 and
+// of D2Q9 load their rows a prefetch distance ahead of the walk
+// (tn_prefetch), which leaves room for taller segments.  Each height is the
+// tallest without scratch memory that measured faster at 4096^2 (D2Q5 FP32
+// BGK 6 rows: 9 % faster than 4; D2Q9 FP32 BGK 5 rows: 7 %; D2Q9 FP64 BGK
+// 6 rows: 8 %; MRT and FP16 storage gain nothing or spill).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
-    if constexpr (NS == 4 && Q == 5) return sizeof(S) == 8 ? 6 : KIND == 1 ? LBW_LY4_MRT : LBW_LY4_BGK;
-    else if constexpr (NS == 2 && Q == 5 && sizeof(S) == 4) return 8;
-    else if constexpr (NS == 3 && Q == 5) return 6;
+    if constexpr (Q == 9) return KIND == 1 ? 4 : sizeof(S) == 8 ? 6 : 5;
+    else if constexpr (sizeof(S) == 2) return 4;
+    else if constexpr (NS == 4) return sizeof(S) == 8 ? 6 : KIND == 1 ? 5 : 6;
+    else if constexpr (NS == 2 && sizeof(S) == 4) return 8;
+    else if constexpr (NS == 3) return 6;
     else return 4;
 }
 
-// Rows the walk keeps loads ahead (0: all rows of the segment at once).
-template <int Q, int NS>
-constexpr int tn_prefetch() { return NS == 4 && Q == 5 ? 6 : 0; }
+// Rows the walk keeps loads ahead (0: all rows of the segment at once;
+// measured 6 better than 4 or 8).
+template <typename S, int Q, int NS, int KIND>
+constexpr int tn_prefetch() {
+    if constexpr (Q == 9) return KIND == 1 ? 0 : 6;
+    else return NS == 4 && sizeof(S) != 2 ? 6 : 0;
+}
 
 // Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch.  The
 // wave takes nrun <= NS steps (FULL: NS, known at compile time): stage s
@@ -223,7 +226,7 @@ template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL>
 __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     using T = typename Tr<S>::T;
     constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS, KIND>(), K = LY + 2 * NS;
-    constexpr int PD = tn_prefetch<Q, NS>();
+    constexpr int PD = tn_prefetch<S, Q, NS, KIND>();
     static_assert(H * V >= NS, "the strip halo must cover one column per step");
     const int nx = p.nx, ny = p.ny;
     const int nstrip = (nx + OW - 1) / OW;
