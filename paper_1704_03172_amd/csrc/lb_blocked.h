@@ -320,6 +320,17 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
             rb = __builtin_amdgcn_readlane(rowv, m - NS);
             re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
         }
+        if (p.rho_out != nullptr && owned_row) {   // rho of time n+st, summed as the one-step kernel does
+            T *rr = reinterpret_cast<T *>(p.rho_out) + (int64_t)(st - 1) * p.rho_stride + (int64_t)gm * nx;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (!own[j]) continue;
+                T rho = T(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) rho += g[i][j];
+                rr[xw[j]] = rho;
+            }
+        }
         Receivers rc = p.rec;
         rc.col = p.rec.col + st - 1;
         T po[Q][V];

@@ -114,6 +114,8 @@ struct StepParams {
     double s_n3 = 0.0;                 // third and fourth steps
     double s_n4 = 0.0;
     int32_t nrun = 1;                  // launch_stepn: steps this launch takes (= ns)
+    int64_t rho_stride = 0;            // launch_stepn with rho_out: elements between the
+                                       // rho fields of consecutive steps
 };
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
@@ -205,8 +207,10 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull,
 // ns pull steps in one launch of the temporally blocked ns-step kernel
 // (p.nrun must equal ns): reads h(n) from p.src, writes h(n + ns) to p.dst
 // (a buffer other than p.src), records columns p.rec.col .. p.rec.col + ns - 1,
-// source amplitudes p.s_n .. p.s_n4.  No reduction partials, rho_out,
-// snapshot or interface work.  2 <= ns <= stepn_max(storage, p.q, p.coll.kind).
+// source amplitudes p.s_n .. p.s_n4; with p.rho_out, the pre-collision rho of
+// time n + s (s = 1..ns) goes to p.rho_out + (s - 1) * p.rho_stride.  No
+// reduction partials, snapshot or interface work.
+// 2 <= ns <= stepn_max(storage, p.q, p.coll.kind).
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
 int stepn_max(int storage, int q, int kind);   // steps per launch the blocked kernel offers (1: none)
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);

@@ -763,10 +763,18 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
 // t+2 .. t+ns.  left: steps still to take in this call; the last launch of
 // a call takes one step (the fields and the saved state of time t are read
 // from h(t-1)).
-int blocked_steps(const lb_grid *h, int64_t left) {
-    if (h->patch || h->sum_rho) return 1;
+// Steps per launch of the blocked kernel for this grid (1: none), capped by
+// the descriptor's steps_per_launch.
+int blocked_max(const lb_grid *h) {
+    if (h->patch) return 1;
     int ns = lbw::stepn_max(h->storage, h->q, h->d.collision);
     if (h->d.steps_per_launch > 0) ns = std::min(ns, h->d.steps_per_launch);
+    return ns;
+}
+
+int blocked_steps(const lb_grid *h, int64_t left) {
+    if (h->patch || h->sum_rho) return 1;
+    int ns = blocked_max(h);
     ns = (int)std::min<int64_t>(ns, left - 1);
     if (h->ckpt_valid)
         for (int k = 2; k <= ns; ++k)
@@ -969,15 +977,28 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
         LB_TRY(h, lbw::launch_copy(g.pop[0], h->ckpt + (size_t)j * state_bytes_main(h), state_bytes_main(h),
                                    h->stream));
         g.cur = 0;
-        for (int64_t m = a; m <= b; ++m) {
+        // the segment's rho fields, up to blocked_max steps per launch (the
+        // collide-only launch of a pre-collision checkpoint takes one)
+        for (int64_t m = a; m <= b;) {
             const bool pull = !(m == a && h->ckpt_pre[(size_t)j]);
             StepParams p = base_params(h, g, true);
             p.src = g.curp();
             p.dst = g.prevp();
             p.s_n = source_at(h, m);
             p.rho_out = (char *)h->seg + (size_t)(m - a) * n_nodes * tsz;
-            LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
+            const int ns = pull ? (int)std::min<int64_t>(blocked_max(h), b - m + 1) : 1;
+            if (ns > 1) {
+                p.s_n2 = source_at(h, m + 1);
+                p.s_n3 = source_at(h, m + 2);
+                p.s_n4 = source_at(h, m + 3);
+                p.nrun = ns;
+                p.rho_stride = n_nodes;
+                LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));
+            } else {
+                LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
+            }
             g.cur = 1 - g.cur;
+            m += ns;
         }
         for (int64_t n = b; n >= a; --n) {
             ap.rho = (char *)h->seg + (size_t)(n - a) * n_nodes * tsz;

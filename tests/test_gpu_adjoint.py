@@ -33,7 +33,7 @@ def make_case(nx=96, ny=64, q=5, collision="bgk", tau=0.5, s=None, N=150, seed=1
     return case
 
 
-def gpu_gradient(case, precision, K=16, c2=None):
+def gpu_gradient(case, precision, K=16, c2=None, steps_per_launch=0):
     import torch
     from paper_1704_03172_amd import lbwave
     N = case["nsteps"]
@@ -41,7 +41,7 @@ def gpu_gradient(case, precision, K=16, c2=None):
                     precision=precision, tau=case["tau"], s=case["s"], ratio=case["ratio"],
                     sponge_width=case["sponge_width"], sponge_sigma_max=case["sponge_sigma_max"],
                     trace_capacity=N + 1, max_receivers=len(case["receivers"]),
-                    ckpt_every=K, ckpt_capacity=N // K + 1)
+                    ckpt_every=K, ckpt_capacity=N // K + 1, steps_per_launch=steps_per_launch)
     g.set_medium(case["c2"] if c2 is None else c2)
     if "rho0" in case:
         g.set_state(case["rho0"], case["jx0"], case["jy0"])
@@ -77,6 +77,21 @@ def test_fp32_gradient_matches_oracle_adjoint():
     err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
     print("FP32 gradient relL2 vs FP64 oracle adjoint: %.2e" % err)
     assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("kw", [dict(), dict(tau=0.8), dict(collision="mrt", s=[1, 1, 1, 1.4, 1.7]),
+                                dict(q=9, collision="mrt", s=[1, 1, 1, 2, 2, 2, 1, 1, 2]), dict(q=9)])
+def test_blocked_recompute_gives_the_same_gradient(precision, kw):
+    """The segment recompute takes several steps per launch (the blocked
+    kernel writing each step's rho) unless steps_per_launch = 1: the
+    gradients are the same bits, with checkpoint spacings that leave every
+    remainder of the steps per launch."""
+    case = make_case(N=97, seed=6, **kw)
+    for K in (13, 16, 98):
+        a = gpu_gradient(case, precision, K=K, steps_per_launch=1)[1]
+        b = gpu_gradient(case, precision, K=K)[1]
+        np.testing.assert_array_equal(a, b)
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient():
