@@ -177,12 +177,18 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
     finite = bool(torch.isfinite(grad).all().item())
     g.close()
     N = n * n
+    ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32")
     return {"workload": "%d shots, %dx%d, %d steps, checkpoints every %d, FP32 state, FP64 gradient"
                         % (nshots, n, n, nsteps, K),
             "seconds_total": round(wall, 3), "ms_per_shot": round(wall / nshots * 1e3, 2),
             "forward_ms_per_shot": round(t_fwd / nshots * 1e3, 2),
             "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
-            "adjoint_phase_GB_s": round((44 + 64) * N * nsteps / (t_adj / nshots) / 1e9, 1),
+            # algorithmic bytes per node and step of the adjoint phase: the
+            # blocked recompute (44 B per ns-step launch plus the 4-byte rho
+            # field of each step) and the adjoint step (lambda in and out,
+            # rho, c^2, FP64 gradient read and written: 64 B)
+            "adjoint_phase_GB_s": round((44.0 / ns_rec + 4 + 64) * N * nsteps / (t_adj / nshots) / 1e9, 1),
+            "recompute_steps_per_launch": ns_rec,
             "misfit": float(phi.item()), "gradient_finite": finite}
 
 

@@ -419,6 +419,22 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
             rhov[j] = rrow[x];
         }
     }
+    // the FP64 gradient of these nodes, read before the arithmetic (16-byte
+    // accesses where the row and nx allow) and written back after it
+    double gv[V];
+    double *grow = p.grad + (int64_t)y * nx;
+    const bool gvec = x0 + V <= nx && (((int64_t)y * nx + x0) & 1) == 0;
+    if (gvec) {
+#pragma unroll
+        for (int j = 0; j < V; j += 2) {
+            const double2 t = *reinterpret_cast<const double2 *>(grow + x0 + j);
+            gv[j] = t.x;
+            gv[j + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) gv[j] = x0 + j < nx ? grow[x0 + j] : 0.0;
+    }
     int rb = 0, re = 0;
     if (p.rec.row_ptr) {
         rb = p.rec.row_ptr[y];
@@ -429,10 +445,19 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         const int x = x0 + j;
-        const T sf = sponge_factor<T>(min(x, nx - 1), y, nx, ny, p.sponge_width, p.sponge_smax);
         T m[Q], nu[Q], w[Q];
+        // (1 - sigma) P^T lambda: outside the sponge the factor is 1 and
+        // mu * 1 = mu, so only nodes inside it multiply
+        const int dedge = edge_dist(min(x, nx - 1), y, nx, ny);
+        if (dedge < p.sponge_width) {
+            asm volatile("");
+            const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) m[i] = mu[i][j] * sf;
+            for (int i = 0; i < Q; ++i) m[i] = mu[i][j] * sf;
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) m[i] = mu[i][j];
+        }
         if (KIND == 0) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) nu[i] = T(p.coll.omega) * m[i];
@@ -504,9 +529,17 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
             for (int i = 0; i < Q; ++i) dl += p.dw[i] * double(lam[i]);
             gacc += double(rhov[j]) * dl;
         }
-        if (x < nx) p.grad[(int64_t)y * nx + x] += gacc;
+        gv[j] += gacc;
 #pragma unroll
         for (int i = 0; i < Q; ++i) outv[i][j] = lam[i];
+    }
+    if (gvec) {
+#pragma unroll
+        for (int j = 0; j < V; j += 2) *reinterpret_cast<double2 *>(grow + x0 + j) = make_double2(gv[j], gv[j + 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            if (x0 + j < nx) grow[x0 + j] = gv[j];
     }
     T *lo = reinterpret_cast<T *>(p.lam);
 #pragma unroll
