@@ -222,7 +222,7 @@ constexpr int tn_prefetch() {
 // wave takes nrun <= NS steps (FULL: NS, known at compile time): stage s
 // (1..nrun) computes h(n+s) from h(n+s-1); the state of stage nrun is
 // stored.
-template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL>
+template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL, bool RHO = false>
 __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     using T = typename Tr<S>::T;
     constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS, KIND>(), K = LY + 2 * NS;
@@ -320,17 +320,10 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
             rb = __builtin_amdgcn_readlane(rowv, m - NS);
             re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
         }
-        if (p.rho_out != nullptr && owned_row) {   // rho of time n+st, summed as the one-step kernel does
-            T *rr = reinterpret_cast<T *>(p.rho_out) + (int64_t)(st - 1) * p.rho_stride + (int64_t)gm * nx;
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                if (!own[j]) continue;
-                T rho = T(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) rho += g[i][j];
-                rr[xw[j]] = rho;
-            }
-        }
+        // rho of time n+st (owned nodes), summed as the one-step kernel does
+        const bool want_rho = RHO && owned_row;   // RHO: p.rho_out is set
+        T *rr = reinterpret_cast<T *>(p.rho_out) + (int64_t)(st - 1) * p.rho_stride + (int64_t)gm * nx;
+        T rhov[V];
         Receivers rc = p.rec;
         rc.col = p.rec.col + st - 1;
         T po[Q][V];
@@ -340,11 +333,32 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
             if (rb < re && own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, C[m][j]);
+            if (want_rho) {
+                T rho = T(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) rho += gj[i];
+                rhov[j] = rho;
+            }
             post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), sn[st - 1], pj,
                                   strip_sponge || min(wm, ny - 1 - wm) < L);
             // rounded to the storage format, as a stored h(n+st) would be
 #pragma unroll
             for (int i = 0; i < Q; ++i) po[i][j] = T(to_store<S>(pj[i]));
+        }
+        if (want_rho) {
+            if constexpr (VEC && V > 1) {
+                if (own[0]) {
+                    typedef typename LaneVec<V, T>::type rt;
+                    rt t;
+#pragma unroll
+                    for (int j = 0; j < V; ++j) t[j] = rhov[j];
+                    *at_lane<rt>(rr, xv) = t;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    if (own[j]) rr[xw[j]] = rhov[j];
+            }
         }
         if (st == nrun) {
             if (owned_row) {   // the result of this launch
@@ -391,11 +405,11 @@ __device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     });
 }
 
-template <typename S, int Q, int KIND, bool VEC, int NS>
+template <typename S, int Q, int KIND, bool VEC, int NS, bool RHO>
 __global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
     // wave-uniform (so that the row and loop arithmetic is scalar)
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    stepn_wave<S, Q, KIND, VEC, NS, true>(p, xcd_block() * (kT2Block / 64) + wib, NS);
+    stepn_wave<S, Q, KIND, VEC, NS, true, RHO>(p, xcd_block() * (kT2Block / 64) + wib, NS);
 }
 
 // Up to NS steps of every active shot in one launch (a shot takes
@@ -479,8 +493,15 @@ hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
         auto launch = [&](auto kc) {
             constexpr int KK = decltype(kc)::value;
             if constexpr (NS <= tn_max<S, Q, KK>()) {
-                if (vec) hipLaunchKernelGGL((k_stepn<S, Q, KK, true, NS>), grid, dim3(kT2Block), 0, s, p);
-                else hipLaunchKernelGGL((k_stepn<S, Q, KK, false, NS>), grid, dim3(kT2Block), 0, s, p);
+                // the rho-writing variant (the adjoint's recompute) is a kernel of
+                // its own, so that the forward kernels carry none of its registers
+                if (p.rho_out != nullptr) {
+                    if (vec) hipLaunchKernelGGL((k_stepn<S, Q, KK, true, NS, true>), grid, dim3(kT2Block), 0, s, p);
+                    else hipLaunchKernelGGL((k_stepn<S, Q, KK, false, NS, true>), grid, dim3(kT2Block), 0, s, p);
+                } else {
+                    if (vec) hipLaunchKernelGGL((k_stepn<S, Q, KK, true, NS, false>), grid, dim3(kT2Block), 0, s, p);
+                    else hipLaunchKernelGGL((k_stepn<S, Q, KK, false, NS, false>), grid, dim3(kT2Block), 0, s, p);
+                }
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
