@@ -22,8 +22,9 @@
 //
 // This one-step kernel serves single steps (the last of a call, sum-of-rho
 // recording, checkpoint boundaries), the refinement patch, whose interface
-// work is fused into it, and the adjoint's forward recompute; runs of steps
-// go to the temporally blocked kernel of lb_blocked.h.  Both take their per-node
+// work is fused into it, and the collide-only first step of an adjoint
+// segment; runs of steps (the adjoint's recompute included) go to the
+// temporally blocked kernel of lb_blocked.h.  Both take their per-node
 // arithmetic from lb_node.h.
 #include "lb_internal.h"
 #include "lb_node.h"
