@@ -415,8 +415,14 @@ __global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
 // Up to NS steps of every active shot in one launch (a shot takes
 // min(NS, bp.max_run, steps left)): wave w belongs to the active shot a with
 // wprefix[a] <= w < wprefix[a+1] (waves of nstrip x nseg per shot).
+// FP32 D2Q5: at most 168 VGPRs, three waves per SIMD (its two bodies would
+// otherwise take one register more for BGK at tau = 1/2 and halve the
+// occupancy); the others keep the compiler's choice.
+template <typename S, int Q>
+constexpr int batch_min_waves() { return Q == 5 && sizeof(S) == 4 ? 3 : 1; }
 template <typename S, int Q, int KIND, int NS>
-__global__ __launch_bounds__(kT2Block) void k_stepn_batch(BatchParams bp) {
+__global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(batch_min_waves<S, Q>())))
+void k_stepn_batch(BatchParams bp) {
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
     if (w >= bp.wprefix[bp.nact]) return;
