@@ -255,8 +255,10 @@ int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res,
  * FP64.  Needs ckpt_every > 0, receivers recorded, no patch, and a forward
  * run of exactly nt steps from lb_set_state (or the rest state) with the
  * same medium and source.  The forward segments are recomputed from the
- * checkpoints; afterwards the population state is no longer the forward
- * state, so stepping again needs lb_set_state or lb_set_raw_state first. */
+ * checkpoints (as many steps per launch as lb_step_n takes; the gradient is
+ * the same bits whatever steps_per_launch says); afterwards the population
+ * state is no longer the forward state, so stepping again needs
+ * lb_set_state or lb_set_raw_state first. */
 int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad);
 
 /* Wait for all work enqueued by the handle; returns the sticky error. */
