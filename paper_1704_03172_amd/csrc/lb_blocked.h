@@ -18,12 +18,12 @@ namespace {
 // ---- NS time steps per launch ---------------------------------------------------
 // Temporal blocking: one pass reads h(n) and writes h(n+NS), so every
 // population element crosses HBM once per NS updates (NS up to 4, see
-// tn_max).  A wavefront owns a strip of columns and a
-// segment of rows: it loads the segment's rows of h(n) plus NS halo rows on
-// each side, all at once (of the outermost halo rows only the population
-// that streams into the segment), then walks down the rows computing
-// h(n+1), ..., h(n+NS) from the rows above, at and below, in registers, and
-// stores each finished row.  Pulls along x come from the neighbouring lane
+// tn_max).  A wavefront owns a strip of columns and a segment of rows: it
+// loads the segment's rows of h(n) plus NS halo rows on each side, all at
+// once or a few rows ahead of the walk (tn_prefetch; of the outermost halo
+// rows only the population that streams into the segment), walks down the
+// rows computing h(n+1), ..., h(n+NS) from the rows above, at and below, in
+// registers, and stores each finished row.  Pulls along x come from the neighbouring lane
 // (DPP lane shifts).  The strip carries H halo lanes on each side (NS
 // columns are needed; see Tb).  Measured on MI355X with copy kernels of
 // this access pattern, waves that stream one row at a time reach only
@@ -43,15 +43,12 @@ template <typename S> struct Tb {
     // work outweighs the unaligned edges once the kernel is not
     // bandwidth-bound)
     static constexpr int H = sizeof(S) == 4 ? 2 : kT2Halo;
-    static constexpr int OW = (64 - 2 * H) * V;                          // owned columns per wave (448 B)
+    static constexpr int OW = (64 - 2 * H) * V;   // owned columns per wave (480 B for FP32, 448 B otherwise)
 };
 
 template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_vector_type(V), aligned(sizeof(S)))); };
 
-// One row (all populations) of the lane's V columns, converted to T.  VEC:
-// one vector access at the lane's wrapped first column xv (the lane's
-// columns are contiguous after the wrap when nx is a multiple of V);
-// otherwise element accesses at the wrapped columns xw.
+// Load with the ordinary cache policy (keep) or nontemporal.
 template <typename U>
 __device__ inline U ld_hint(const U *p, bool keep) {
     return keep ? *p : __builtin_nontemporal_load(p);
@@ -66,6 +63,11 @@ __device__ inline U *at_lane(E *row, int x) {
         std::conditional_t<std::is_const_v<E>, const char, char> *>(row) + (uint32_t)x * (uint32_t)sizeof(E));
 }
 
+// One row (all populations) of the lane's V columns, converted to T.  VEC:
+// one vector access at the lane's wrapped first column xv (the lane's
+// columns are contiguous after the wrap when nx is a multiple of V);
+// otherwise element accesses at the wrapped columns xw.  SEL > 0 / < 0:
+// only the populations that move toward +y / -y (c_y = +1 / -1).
 template <bool VEC, int SEL, bool KEEP, typename S, typename T, int Q, int V>
 __device__ inline void load_row2(const S *__restrict__ base, int64_t pstride, int64_t rowoff, int xv,
                                  const int (&xw)[V], T (&out)[Q][V]) {
