@@ -182,31 +182,31 @@ __device__ inline A &pick4(A &a0, A &a1, A &a2, A &a3) {
 }
 
 // Steps per launch the blocked kernel offers for a configuration: the most
-// whose per-stage row state still fits in registers without scratch memory
-// (measured at 4096^2 on MI355X, each count was faster than the one below
-// it).  1: not offered (D2Q9 with FP16 storage, whose 4-column lanes would
-// hold their rows in scratch).
+// that measured faster at 4096^2 on MI355X without scratch memory.  1: not
+// offered (D2Q9 with FP16 storage, whose 4-column lanes would hold nine
+// populations per row).
 template <typename S, int Q, int KIND>
 constexpr int tn_max() {
-    if constexpr (sizeof(S) == 2) return Q == 5 ? 2 : 1;
+    if constexpr (sizeof(S) == 2) return Q == 5 ? 3 : 1;
     else if constexpr (Q == 9 && sizeof(S) == 4) return KIND == 1 ? 2 : 3;
     else return 4;
 }
 
 // Rows per segment for NS steps: the segment rows plus NS halo rows on each
-// side sit in registers (K = rows + 2 NS rows per stage), so more steps and
-// larger per-row states (D2Q9, FP16 storage with 4 columns per lane, the MRT
-// collision) take shorter segments.  The BGK kernels of four-step D2Q5 and
-// of D2Q9 load their rows a prefetch distance ahead of the walk
-// (tn_prefetch), which leaves room for taller segments.  Each height is the
-// tallest without scratch memory that measured faster at 4096^2 (D2Q5 FP32
-// BGK 6 rows: 9 % faster than 4; D2Q9 FP32 BGK 5 rows: 7 %; D2Q9 FP64 BGK
-// 6 rows: 8 %; MRT and FP16 storage gain nothing or spill).
+// side are in flight in registers, so more steps and larger per-row states
+// take shorter segments.  Most configurations load their rows a prefetch
+// distance ahead of the walk (tn_prefetch), which bounds the rows in flight
+// and leaves room for taller segments.  Each height is the tallest that
+// measured faster at 4096^2 while the kernel stays at three waves per SIMD
+// (at most 168 VGPRs) where it was there before (D2Q5 FP32 6 rows: 9 %
+// faster than 4, 7 rows crossing to two waves: 8 % slower; D2Q9 FP32 BGK 5
+// rows: 7 %; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows: 10 %; FP16
+// storage 5 rows with three steps: 3 %).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
-    if constexpr (Q == 9) return KIND == 1 ? 4 : sizeof(S) == 8 ? 6 : 5;
-    else if constexpr (sizeof(S) == 2) return 4;
-    else if constexpr (NS == 4) return sizeof(S) == 8 ? 6 : KIND == 1 ? 5 : 6;
+    if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 4) : sizeof(S) == 8 ? 6 : 5;
+    else if constexpr (sizeof(S) == 2) return 5;
+    else if constexpr (NS == 4) return 6;
     else if constexpr (NS == 2 && sizeof(S) == 4) return 8;
     else if constexpr (NS == 3) return 6;
     else return 4;
@@ -216,8 +216,9 @@ constexpr int tn_rows() {
 // measured 6 better than 4 or 8).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_prefetch() {
-    if constexpr (Q == 9) return KIND == 1 ? 0 : 6;
-    else return NS == 4 && sizeof(S) != 2 ? 6 : 0;
+    if constexpr (Q == 9) return KIND == 1 && sizeof(S) == 4 ? 0 : 6;
+    else if constexpr (sizeof(S) == 2) return 6;
+    else return NS == 4 ? 6 : 0;
 }
 
 // Wave `wave` (of nstrip * nseg for this grid) of an NS-step launch.  The
@@ -225,7 +226,7 @@ constexpr int tn_prefetch() {
 // (1..nrun) computes h(n+s) from h(n+s-1); the state of stage nrun is
 // stored.
 template <typename S, int Q, int KIND, bool VEC, int NS, bool FULL, bool RHO = false>
-__device__ inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
+__device__ __attribute__((always_inline)) inline void stepn_wave(const StepParams &p, int wave, int nrun_arg) {
     using T = typename Tr<S>::T;
     constexpr int V = Tb<S>::V, H = Tb<S>::H, OW = Tb<S>::OW, LY = tn_rows<S, Q, NS, KIND>(), K = LY + 2 * NS;
     constexpr int PD = tn_prefetch<S, Q, NS, KIND>();

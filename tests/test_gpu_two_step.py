@@ -115,19 +115,22 @@ def test_segment_edges(ny):
     segment, a single segment, rows that wrap into the next segment and
     grids shorter than the halo): D2Q5 FP32 BGK with four steps (6-row
     segments, rows loaded six ahead of the walk), D2Q5 FP32 MRT with four
-    (5 rows), D2Q5 FP32 with three (6 rows) and two (8 rows), D2Q5 FP64 MRT
-    with four (6 rows), D2Q9 BGK FP32 with three (5 rows, prefetched), D2Q9
-    BGK FP64 with four (6 rows, prefetched) and D2Q9 MRT FP32 with two
-    (4 rows), so that every direction crosses the segment edges."""
+    (6 rows), D2Q5 FP32 with three (6 rows) and two (8 rows), D2Q5 FP64 MRT
+    with four (6 rows), D2Q5 FP16 storage with three (5 rows), D2Q9 BGK FP32
+    with three (5 rows), D2Q9 BGK FP64 with four (6 rows), D2Q9 MRT FP32
+    with two (4 rows) and D2Q9 MRT FP64 with four (5 rows), so that every
+    direction crosses the segment edges."""
     mrt9 = [1, 1, 1, 2, 2, 2, 1, 1, 2]
     mrt5 = [1, 1, 1, 1.6, 1.3]
     for q, coll, s, prec, spl in ((5, "bgk", None, "f32", 0), (5, "mrt", mrt5, "f32", 0), (5, "bgk", None, "f32", 3),
-                                  (5, "bgk", None, "f32", 2), (5, "mrt", mrt5, "f64", 0),
-                                  (9, "bgk", None, "f32", 0), (9, "bgk", None, "f64", 0), (9, "mrt", mrt9, "f32", 0)):
+                                  (5, "bgk", None, "f32", 2), (5, "mrt", mrt5, "f64", 0), (5, "bgk", None, "f16s", 0),
+                                  (9, "bgk", None, "f32", 0), (9, "bgk", None, "f64", 0), (9, "mrt", mrt9, "f32", 0),
+                                  (9, "mrt", mrt9, "f64", 0)):
         case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2 if ny > 4 else 0)
         case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
         two = both(case, prec, spl=spl)
-        compare(case, prec, gpu=two)
+        if prec != "f16s":
+            compare(case, prec, gpu=two)
 
 
 def test_chunked_calls_mix_one_and_two_step_launches():
