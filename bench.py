@@ -185,9 +185,10 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
             "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
             # algorithmic bytes per node and step of the adjoint phase: the
             # blocked recompute (44 B per ns-step launch plus the 4-byte rho
-            # field of each step) and the adjoint step (lambda in and out,
-            # rho, c^2, FP64 gradient read and written: 64 B)
-            "adjoint_phase_GB_s": round((44.0 / ns_rec + 4 + 64) * N * nsteps / (t_adj / nshots) / 1e9, 1),
+            # field of each step) and the two-step adjoint launch (lambda in
+            # and out, c^2 and the FP64 gradient read and written once per two
+            # steps, rho of both: 68 B per two steps)
+            "adjoint_phase_GB_s": round((44.0 / ns_rec + 4 + 68 / 2.0) * N * nsteps / (t_adj / nshots) / 1e9, 1),
             "recompute_steps_per_launch": ns_rec,
             "misfit": float(phi.item()), "gradient_finite": finite}
 

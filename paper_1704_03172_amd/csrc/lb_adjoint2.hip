@@ -1,0 +1,217 @@
+// lb_adjoint2.hip -- two backward steps of the discrete adjoint per launch
+// (steps n and n-1 of the segment sweep in lb_adjoint), with the strip and
+// segment decomposition of the blocked forward kernel (lb_blocked.h): a
+// wavefront loads the rows of lambda(n+1) of its segment plus two halo rows
+// on each side, computes lambda(n) on the segment and one halo row on each
+// side (receiver residuals included, as the second step reads them), then
+// lambda(n-1) on its own rows, which it stores.  The FP64 gradient of the
+// owned nodes is read once, takes the terms of time n and then of time n-1
+// (the order of two one-step launches) and is written once.  Per node the
+// arithmetic is adjoint_node (lb_node.h), as in the one-step kernel, so the
+// gradient is the same bits; lambda crosses HBM once per two steps.
+#include "lb_blocked.h"
+
+namespace lbw {
+namespace {
+
+// Rows per segment (the two halo rows of each side are computed twice).
+template <typename T, int Q>
+constexpr int adj2_rows() { return Q == 5 ? 4 : 2; }
+
+// mu_i(x) = lambda_i(n+1)(x + c_i): the transpose of the pull, from the row
+// below for c_y = +1 (D), above for c_y = -1 (U), and the lane to the right
+// (x + 1) or left (x - 1) along x.
+template <typename T, int Q, int V>
+__device__ inline void pull_back_row(const T (&U)[Q][V], const T (&C)[Q][V], const T (&D)[Q][V], T (&g)[Q][V]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T r[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) r[j] = cyv<Q>(i) > 0 ? D[i][j] : cyv<Q>(i) < 0 ? U[i][j] : C[i][j];
+        if (cxv<Q>(i) > 0) {          // from x + 1
+            const T rr = from_upper(r[0]);
+#pragma unroll
+            for (int j = 0; j < V - 1; ++j) g[i][j] = r[j + 1];
+            g[i][V - 1] = rr;
+        } else if (cxv<Q>(i) < 0) {   // from x - 1
+            const T l = from_lower(r[V - 1]);
+#pragma unroll
+            for (int j = V - 1; j > 0; --j) g[i][j] = r[j - 1];
+            g[i][0] = l;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) g[i][j] = r[j];
+        }
+    }
+}
+
+template <typename T, int Q, int KIND, bool VEC>
+__device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointParams &p, int wave) {
+    constexpr int V = Tb<T>::V, H = Tb<T>::H, OW = Tb<T>::OW, LY = adj2_rows<T, Q>(), K = LY + 4;
+    static_assert(H * V >= 2, "the strip halo must cover one column per step");
+    const int nx = p.nx, ny = p.ny;
+    const int nstrip = (nx + OW - 1) / OW;
+    const int nseg = (ny + LY - 1) / LY;
+    if ((int64_t)wave >= (int64_t)nstrip * nseg) return;   // whole waves
+    const int lane = threadIdx.x & 63;
+    const int sx = wave % nstrip, sy = wave / nstrip;
+    const int xl = sx * OW - H * V + lane * V;
+    const int y0 = sy * LY, y1 = min(y0 + LY, ny);
+    int xw[V], dxw[V];
+    bool own[V];
+    const bool own_lane = lane >= H && lane < 64 - H;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        xw[j] = wrapi(xl + j, nx);
+        own[j] = own_lane && xl + j < nx;
+        dxw[j] = min(xw[j], nx - 1 - xw[j]);
+    }
+    const int xv = xw[0];
+    // receiver rows of walk rows 1 .. K-2 (grid rows y0-1 .. y0+LY): lane k
+    // holds the CSR range of walk row k + 1
+    int rb_l = 0, re_l = 0;
+    if (p.rec.row_ptr != nullptr && lane < (y1 - y0) + 2) {
+        const int w = wrapi(y0 - 1 + lane, ny);
+        rb_l = p.rec.row_ptr[w];
+        re_l = p.rec.row_ptr[w + 1];
+    }
+    int wr = wrapi(y0 - 2, ny);
+    int wrow[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        wrow[k] = wr;
+        wr = wr + 1 == ny ? 0 : wr + 1;
+    }
+    const T *ln = reinterpret_cast<const T *>(p.lam_next);
+    const T *c2 = reinterpret_cast<const T *>(p.c2);
+    T L0[K][Q][V], L1[K][Q][V], C[K][V];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t ro = (int64_t)wrow[k] * nx;
+        if (k < 4 || k >= K - 4) load_row2<VEC, 0, true, T, T, Q, V>(ln, p.pstride, ro, xv, xw, L0[k]);
+        else load_row2<VEC, 0, false, T, T, Q, V>(ln, p.pstride, ro, xv, xw, L0[k]);
+        if (k >= 1 && k <= K - 2) load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
+    }
+    // rho of times n and n-1 and the FP64 gradient at the owned nodes
+    T R1[LY][V], R2[LY][V];
+    double G[LY][V];
+    const T *rho1 = reinterpret_cast<const T *>(p.rho);
+    const T *rho2 = reinterpret_cast<const T *>(p.rho_prev);
+#pragma unroll
+    for (int r = 0; r < LY; ++r) {
+        const int gm = min(y0 + r, y1 - 1);   // rows past a short last segment repeat its last row (unused)
+        const int64_t ro = (int64_t)gm * nx;
+        load_c2row<VEC, false, T, V>(rho1, ro, xv, xw, R1[r]);
+        load_c2row<VEC, false, T, V>(rho2, ro, xv, xw, R2[r]);
+#pragma unroll
+        for (int j = 0; j < V; ++j) G[r][j] = own[j] ? p.grad[ro + xw[j]] : 0.0;
+    }
+
+    // step st (1: time n, 2: time n-1) at walk row m (grid row y0 - 2 + m)
+    auto stage = [&](auto stc, auto mc) __attribute__((always_inline)) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int m = decltype(mc)::value;
+        const int gm = y0 - 2 + m;
+        const bool owned_row = gm >= y0 && gm < y1;
+        if (st == 2 && !owned_row) return;
+        const int wm = wrow[m];
+        auto &A = st == 1 ? L0 : L1;
+        T mu[Q][V];
+        pull_back_row<T, Q, V>(A[m - 1], A[m], A[m + 1], mu);
+        const int rb = __builtin_amdgcn_readlane(rb_l, m - 1), re = __builtin_amdgcn_readlane(re_l, m - 1);
+        const int64_t col = st == 1 ? p.rec.col : p.rec.col - 1;
+        const double sn = st == 1 ? p.s_n : p.s_prev;
+        const bool initial = st == 2 && p.initial_prev != 0;
+        T lo[Q][V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            T muj[Q], lam[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) muj[i] = mu[i][j];
+            T rho = T(0);   // rho only feeds the gradient, kept at the owned rows
+            if constexpr (m >= 2 && m - 2 < LY) {
+                if (owned_row) rho = st == 1 ? R1[m - 2][j] : R2[m - 2][j];
+            }
+            const double g = adjoint_node<T, Q, KIND>(p, muj, C[m][j], rho, xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)),
+                                                      rb, re, col, sn, initial, lam);
+            if constexpr (m >= 2 && m - 2 < LY) {
+                if (owned_row && own[j]) G[m - 2][j] += g;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lo[i][j] = lam[i];
+        }
+        if constexpr (st == 1) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int j = 0; j < V; ++j) L1[m][i][j] = lo[i][j];
+        } else {
+            T *out = reinterpret_cast<T *>(p.lam);
+            const int64_t ro = (int64_t)gm * nx;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                T *r = out + i * p.pstride + ro;
+                if constexpr (VEC && V > 1) {
+                    if (own[0]) {
+                        typedef typename LaneVec<V, T>::type vt;
+                        vt t;
+#pragma unroll
+                        for (int j = 0; j < V; ++j) t[j] = lo[i][j];
+                        __builtin_nontemporal_store(t, at_lane<vt>(r, xv));
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        if (own[j]) __builtin_nontemporal_store(lo[i][j], r + xw[j]);
+                }
+            }
+        }
+    };
+    static_for<2, K>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k - 1 >= 1 && k - 1 <= K - 2)
+            stage(std::integral_constant<int, 1>{}, std::integral_constant<int, k - 1>{});
+        if constexpr (k - 2 >= 2 && k - 2 <= K - 3)
+            stage(std::integral_constant<int, 2>{}, std::integral_constant<int, k - 2>{});
+    });
+#pragma unroll
+    for (int r = 0; r < LY; ++r) {
+        if (y0 + r >= y1) continue;
+        const int64_t ro = (int64_t)(y0 + r) * nx;
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+            if (own[j]) p.grad[ro + xw[j]] = G[r][j];
+    }
+}
+
+template <typename T, int Q, int KIND, bool VEC>
+__global__ __launch_bounds__(kT2Block) void k_adjoint2(AdjointParams p) {
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    adj2_wave<T, Q, KIND, VEC>(p, xcd_block() * (kT2Block / 64) + wib);
+}
+
+template <typename T, int Q>
+hipError_t adjoint2_launch(const AdjointParams &p, hipStream_t s) {
+    constexpr int OW = Tb<T>::OW, LY = adj2_rows<T, Q>();
+    const int64_t waves = (int64_t)((p.nx + OW - 1) / OW) * ((p.ny + LY - 1) / LY);
+    const dim3 grid((unsigned)((waves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const bool vec = p.nx % Tb<T>::V == 0, mrt = p.coll.kind == 1;
+    if (mrt) {
+        if (vec) hipLaunchKernelGGL((k_adjoint2<T, Q, 1, true>), grid, dim3(kT2Block), 0, s, p);
+        else hipLaunchKernelGGL((k_adjoint2<T, Q, 1, false>), grid, dim3(kT2Block), 0, s, p);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_adjoint2<T, Q, 0, true>), grid, dim3(kT2Block), 0, s, p);
+        else hipLaunchKernelGGL((k_adjoint2<T, Q, 0, false>), grid, dim3(kT2Block), 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint2(int storage, const AdjointParams &p, hipStream_t s) {
+    if (p.nx < 1 || p.ny < 1 || p.terminal || p.rec.col < 1 || (p.q != 5 && p.q != 9)) return hipErrorInvalidValue;
+    if (storage == ST_F64) return p.q == 5 ? adjoint2_launch<double, 5>(p, s) : adjoint2_launch<double, 9>(p, s);
+    return p.q == 5 ? adjoint2_launch<float, 5>(p, s) : adjoint2_launch<float, 9>(p, s);
+}
+
+}  // namespace lbw

@@ -139,6 +139,11 @@ struct AdjointParams {
     Receivers rec;                     // tables + residual array in `traces`
     int32_t terminal = 0;              // 1: n = N (no step, lambda(N+1) = 0)
     int32_t initial = 0;               // 1: n = 0, add the initial-state term
+    // launch_adjoint2 (steps n = rec.col and n - 1): rho(n - 1), S(n - 1),
+    // and whether n - 1 = 0
+    const void *rho_prev = nullptr;
+    double s_prev = 0.0;
+    int32_t initial_prev = 0;
 };
 
 // Field extraction: one field of the state at the current time.
@@ -190,6 +195,10 @@ struct BatchParams {
 
 // Launchers (lb_kernels.hip).  All return the launch status.
 hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s);
+// Two backward steps (n = p.rec.col and n - 1, 1 <= n < N) in one launch:
+// lambda(n+1) from p.lam_next, lambda(n-1) to p.lam, rho(n) in p.rho and
+// rho(n-1) in p.rho_prev; the gradient gets the terms of n, then of n - 1.
+hipError_t launch_adjoint2(int storage, const AdjointParams &p, hipStream_t s);
 hipError_t launch_misfit(int storage, const void *traces, const void *obs, void *res, int32_t nrec,
                          int64_t cap, int64_t ncols, double *phi, hipStream_t s);
 int step_vwidth(int storage);

@@ -441,95 +441,16 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
         rb = p.rec.row_ptr[y];
         re = p.rec.row_ptr[y + 1];
     }
-    const T *res = reinterpret_cast<const T *>(p.rec.traces);
     T outv[Q][V];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         const int x = x0 + j;
-        T m[Q], nu[Q], w[Q];
-        // (1 - sigma) P^T lambda: outside the sponge the factor is 1 and
-        // mu * 1 = mu, so only nodes inside it multiply
-        const int dedge = edge_dist(min(x, nx - 1), y, nx, ny);
-        if (dedge < p.sponge_width) {
-            asm volatile("");
-            const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
+        T muj[Q], lam[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) m[i] = mu[i][j] * sf;
-        } else {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) m[i] = mu[i][j];
-        }
-        if (KIND == 0) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) nu[i] = T(p.coll.omega) * m[i];
-        } else {
-            T r[9];
-#pragma unroll
-            for (int k = 3; k < Q; ++k) {
-                T a = T(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int c = mrow<Q>(k, i);
-                    if (c != 0) a += T(c) * m[i];
-                }
-                r[k] = T(p.coll.srate[k]) * a;
-            }
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                T a = T(0);
-#pragma unroll
-                for (int k = 3; k < Q; ++k) {
-                    const int c = mrow<Q>(k, i);
-                    if (c != 0) a += T(c) * r[k];
-                }
-                nu[i] = a;
-            }
-        }
-        double gacc = 0.0;
-        {
-            double dn = 0.0, dm = 0.0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                dn += p.dw[i] * double(nu[i]);
-                dm += p.dw[i] * double(m[i]);
-            }
-            gacc += double(rhov[j]) * dn;
-            if (y == p.src_y && x == p.src_x) gacc += p.s_n * dm;
-        }
-        weights<T, Q>(c2v[j], p.coll, w);
-        T s0 = T(0), sxv = T(0), syv = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            s0 += w[i] * nu[i];
-            const T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(p.coll.kax) : T(p.coll.kdg));
-            if (i > 0) {
-                sxv += kj * T(cxv<Q>(i)) * nu[i];
-                syv += kj * T(cyv<Q>(i)) * nu[i];
-            }
-        }
-        T lam[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            lam[i] = m[i] - nu[i] + s0 + T(cxv<Q>(i)) * sxv + T(cyv<Q>(i)) * syv;
-        if (rb < re && x < nx) {
-            int lo = rb, hi = re;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
-            }
-            for (; lo < re && p.rec.xs[lo] == x; ++lo) {
-                const T rr = res[(int64_t)p.rec.slot[lo] * p.rec.cap + p.rec.col];
-#pragma unroll
-                for (int i = 0; i < Q; ++i) lam[i] += c2v[j] * rr;
-                gacc += double(rr) * double(rhov[j]);
-            }
-        }
-        if (p.initial) {
-            double dl = 0.0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) dl += p.dw[i] * double(lam[i]);
-            gacc += double(rhov[j]) * dl;
-        }
+        for (int i = 0; i < Q; ++i) muj[i] = mu[i][j];
+        const double gacc = adjoint_node<T, Q, KIND>(p, muj, c2v[j], rhov[j], x, y, edge_dist(min(x, nx - 1), y, nx, ny),
+                                                     x < nx ? rb : 0, x < nx ? re : 0, p.rec.col, p.s_n, p.initial != 0,
+                                                     lam);
         gv[j] += gacc;
 #pragma unroll
         for (int i = 0; i < Q; ++i) outv[i][j] = lam[i];

@@ -321,5 +321,101 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
     }
 }
 
+// One node of the backward step of time n (the discrete adjoint; see
+// k_adjoint): mu is lambda(n+1) pulled back to the node (before the sponge),
+// dedge the node's distance to the nearest edge, [rb, re) its row's
+// receiver entries (empty: none), col = n for the residuals, s_n = S(n),
+// initial: n = 0.  Writes lambda(n) and returns the node's gradient term of
+// time n (FP64).  Shared by the one-step and the two-step adjoint kernels,
+// so both give the same bits.
+template <typename T, int Q, int KIND>
+__device__ inline double adjoint_node(const AdjointParams &p, const T (&mu)[Q], T c2, T rho, int x, int y, int dedge,
+                                      int rb, int re, int64_t col, double s_n, bool initial, T (&lam)[Q]) {
+    const T *res = reinterpret_cast<const T *>(p.rec.traces);
+    T m[Q], nu[Q], w[Q];
+    // (1 - sigma) P^T lambda: outside the sponge the factor is 1 and
+    // mu * 1 = mu, so only nodes inside it multiply
+    if (dedge < p.sponge_width) {
+        asm volatile("");
+        const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) m[i] = mu[i] * sf;
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) m[i] = mu[i];
+    }
+    if (KIND == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) nu[i] = T(p.coll.omega) * m[i];
+    } else {
+        T r[9];
+#pragma unroll
+        for (int k = 3; k < Q; ++k) {
+            T a = T(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int c = mrow<Q>(k, i);
+                if (c != 0) a += T(c) * m[i];
+            }
+            r[k] = T(p.coll.srate[k]) * a;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T a = T(0);
+#pragma unroll
+            for (int k = 3; k < Q; ++k) {
+                const int c = mrow<Q>(k, i);
+                if (c != 0) a += T(c) * r[k];
+            }
+            nu[i] = a;
+        }
+    }
+    double gacc = 0.0;
+    {
+        double dn = 0.0, dm = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            dn += p.dw[i] * double(nu[i]);
+            dm += p.dw[i] * double(m[i]);
+        }
+        gacc += double(rho) * dn;
+        if (y == p.src_y && x == p.src_x) gacc += s_n * dm;
+    }
+    weights<T, Q>(c2, p.coll, w);
+    T s0 = T(0), sxv = T(0), syv = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        s0 += w[i] * nu[i];
+        const T kj = Q == 5 ? T(0.5) : (i <= 4 ? T(p.coll.kax) : T(p.coll.kdg));
+        if (i > 0) {
+            sxv += kj * T(cxv<Q>(i)) * nu[i];
+            syv += kj * T(cyv<Q>(i)) * nu[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        lam[i] = m[i] - nu[i] + s0 + T(cxv<Q>(i)) * sxv + T(cyv<Q>(i)) * syv;
+    if (rb < re) {
+        int lo = rb, hi = re;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (p.rec.xs[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        for (; lo < re && p.rec.xs[lo] == x; ++lo) {
+            const T rr = res[(int64_t)p.rec.slot[lo] * p.rec.cap + col];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) lam[i] += c2 * rr;
+            gacc += double(rr) * double(rho);
+        }
+    }
+    if (initial) {
+        double dl = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dl += p.dw[i] * double(lam[i]);
+        gacc += double(rho) * dl;
+    }
+    return gacc;
+}
+
 }  // namespace
 }  // namespace lbw

@@ -1000,7 +1000,9 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
             g.cur = 1 - g.cur;
             m += ns;
         }
-        for (int64_t n = b; n >= a; --n) {
+        // backward through the segment, two steps per launch where both lie
+        // in it (and not at the terminal time)
+        for (int64_t n = b; n >= a;) {
             ap.rho = (char *)h->seg + (size_t)(n - a) * n_nodes * tsz;
             ap.terminal = n == nt;
             ap.initial = n == 0;
@@ -1008,7 +1010,16 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
             ap.lam = h->lam[1 - cur_lam];
             ap.s_n = source_at(h, n);
             ap.rec.col = n;
-            LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
+            if (n != nt && n - 1 >= a && blocked_max(h) >= 2) {
+                ap.rho_prev = (char *)h->seg + (size_t)(n - 1 - a) * n_nodes * tsz;
+                ap.s_prev = source_at(h, n - 1);
+                ap.initial_prev = n - 1 == 0;
+                LB_TRY(h, lbw::launch_adjoint2(h->storage, ap, h->stream));
+                n -= 2;
+            } else {
+                LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
+                n -= 1;
+            }
             cur_lam = 1 - cur_lam;
         }
     }
