@@ -329,25 +329,61 @@ __device__ __attribute__((always_inline)) inline void stepn_wave(const StepParam
         T rhov[V];
         Receivers rc = p.rec;
         rc.col = p.rec.col + st - 1;
-        T po[Q][V];
+        // receivers, source and sponge: one wave-uniform test per row, the
+        // per-node work (the same as post_node's) only in rows that have it
+        if (rb < re) {
+            asm volatile("");
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                T gj[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+                if (own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, C[m][j]);
+            }
+        }
+        T pj[V][Q];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            T gj[Q], pj[Q];
+            T gj[Q], w[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
-            if (rb < re && own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, C[m][j]);
             if (want_rho) {
                 T rho = T(0);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) rho += gj[i];
                 rhov[j] = rho;
             }
-            post_node<T, Q, KIND>(p, gj, C[m][j], xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)), sn[st - 1], pj,
-                                  strip_sponge || min(wm, ny - 1 - wm) < L);
-            // rounded to the storage format, as a stored h(n+st) would be
-#pragma unroll
-            for (int i = 0; i < Q; ++i) po[i][j] = T(to_store<S>(pj[i]));
+            collide<T, Q, KIND>(gj, C[m][j], p.coll, pj[j], w);
         }
+        if (wm == p.src_y) {
+            asm volatile("");
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (xw[j] == p.src_x) {
+                    T w[Q];
+                    weights<T, Q>(C[m][j], p.coll, w);
+                    add_source<T, Q>(w, sn[st - 1], pj[j]);
+                }
+            }
+        }
+        const int dy = min(wm, ny - 1 - wm);
+        if (strip_sponge || dy < L) {
+            asm volatile("");
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int d = min(dxw[j], dy);
+                if (d < L) {
+                    asm volatile("");
+                    apply_sponge<T, Q>(d, L, p.sponge_smax, pj[j]);
+                }
+            }
+        }
+        // rounded to the storage format, as a stored h(n+st) would be
+        T po[Q][V];
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) po[i][j] = T(to_store<S>(pj[j][i]));
         if (want_rho) {
             if constexpr (VEC && V > 1) {
                 if (own[0]) {

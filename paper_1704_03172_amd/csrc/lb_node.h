@@ -288,6 +288,23 @@ __device__ inline void record_node(const Receivers &rc, int rb, int re, int x, c
         write_fields<T>(rc, rc.slot[lo], rho, jx, jy, c2);
 }
 
+// The point source w_i S added to a post-collision state (Sec. II D).
+template <typename T, int Q>
+__device__ inline void add_source(const T (&w)[Q], double s_n, T (&gs)[Q]) {
+    const T sn = T(s_n);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
+}
+
+// The sponge factor of a node at distance d < L from the nearest edge
+// applied to its post-collision state.
+template <typename T, int Q>
+__device__ inline void apply_sponge(int d, int L, double smax, T (&gs)[Q]) {
+    const T sf = sponge_at<T>(d, L, smax);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gs[i] = gs[i] * sf;
+}
+
 // Post-collision state of node (x, y): collision, source w_i S at the source
 // node, sponge (dedge: the node's distance to the nearest grid edge).
 // maybe_sponge: wave-uniform; false when no node of the wave's current row
@@ -301,24 +318,17 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
         // (the empty asm keeps this a branch: otherwise the compiler turns
         // the injection into selects evaluated at every node)
         asm volatile("");
-        if (x == p.src_x) {
-            const T sn = T(s_n);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) gs[i] += w[i] * sn;
-        }
+        if (x == p.src_x) add_source<T, Q>(w, s_n, gs);
     }
     // sponge: outside it the factor is 1 and g * 1 = g, so only nodes inside
     // multiply (a branch, kept by the empty asm, rather than selects at
     // every node)
     if (maybe_sponge && dedge < p.sponge_width) {
         asm volatile("");
-        const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) out[i] = gs[i] * sf;
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) out[i] = gs[i];
+        apply_sponge<T, Q>(dedge, p.sponge_width, p.sponge_smax, gs);
     }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = gs[i];
 }
 
 // One node of the backward step of time n (the discrete adjoint; see
