@@ -7,9 +7,9 @@ launch.  The blocked kernel must give the same bits as launches of the
 one-step kernel: the tests below compare the paths bitwise over lattices,
 collisions, storage formats, caps of 2 and 3 steps, grid shapes that leave
 ragged wavefront strips and segments (of 4, 6 and 8 rows), step counts of
-every remainder and chunked calls, with receivers on strip and segment
-boundaries and on the periodic seam, and hold the blocked path to the FP64
-oracle bars.
+every remainder and chunked calls, with receivers and the source on strip
+and segment boundaries and on the periodic seam, and hold the blocked path
+to the FP64 oracle bars.
 """
 import numpy as np
 import pytest
@@ -107,6 +107,31 @@ def test_two_step_shapes(precision, nx, ny):
                                                       dtype=np.int32), boundary_receivers(nx, ny)])}
         two = both(case, precision)
         compare(case, precision, gpu=two)
+
+
+# source nodes on strip edges (owned widths 120, 56 and 224), on 5-, 6- and
+# 8-row segment edges, on the periodic seam and inside the sponge (where the
+# source is added before the sponge factor multiplies the node)
+EDGE_SOURCES = [(119, 5), (120, 6), (55, 11), (56, 12), (223, 24), (224, 25), (239, 15), (240, 16),
+                (0, 0), (699, 44), (121, 1), (300, 43), (350, 17), (351, 18)]
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("q,collision,s", [(5, "bgk", None), (5, "mrt", [1, 1, 1, 1.6, 1.3]), (9, "bgk", None)])
+def test_source_on_strip_and_segment_edges(precision, q, collision, s):
+    """The source row is tested once per row (wave-uniform) in the blocked
+    kernel, also where the row is a halo row that a neighbouring wave
+    recomputes: every placement gives the bits of one step per launch."""
+    if q == 9 and precision == "f16s":
+        pytest.skip("D2Q9 with FP16 storage takes one step per launch")
+    for k, src in enumerate(EDGE_SOURCES):
+        case = layered_case(700, 45, q=q, collision=collision, s=s, nsteps=23, sponge=3)
+        case["source"] = src
+        case["wavelet"] = 1e2 * case["wavelet"]
+        case["receivers"] = np.concatenate([case["receivers"], np.array([src], dtype=np.int32)])
+        two = both(case, precision)
+        if precision == "f64" and k % 5 == 0:
+            compare(case, precision, gpu=two)
 
 
 @pytest.mark.parametrize("ny", [3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18, 19, 23, 40])
