@@ -199,9 +199,10 @@ constexpr int tn_max() {
 // and leaves room for taller segments.  Each height is the tallest that
 // measured faster at 4096^2 while the kernel stays at three waves per SIMD
 // (at most 168 VGPRs) where it was there before (D2Q5 FP32 6 rows: 9 %
-// faster than 4, 7 rows crossing to two waves: 8 % slower; D2Q9 FP32 BGK 5
-// rows: 7 %; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows: 10 %; FP16
-// storage 5 rows with three steps: 3 %).
+// faster than 4, 7 rows within 0.1 % for BGK at tau = 1/2 and 8 rows no
+// faster; D2Q9 FP32 BGK 5 rows: 7 % faster than 4, 3 rows at three waves
+// per SIMD 2.5 % slower; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows:
+// 10 %; FP16 storage 5 rows with three steps: 3 %).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
     if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 4) : sizeof(S) == 8 ? 6 : 5;
@@ -518,11 +519,12 @@ hipError_t by_steps(int ns, F &&f) {
 template <typename S, int Q>
 int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
     int ly = 1;
-    by_steps<S, Q>(ns, [&](auto nc) {
+    const hipError_t e = by_steps<S, Q>(ns, [&](auto nc) {
         constexpr int NS = decltype(nc)::value;
         ly = kind == 1 ? tn_rows<S, Q, NS, 1>() : tn_rows<S, Q, NS, 0>();
         return hipSuccess;
     });
+    if (e != hipSuccess) return 0;   // a step count without a kernel: no waves
     return (int64_t)((nx + Tb<S>::OW - 1) / Tb<S>::OW) * ((ny + ly - 1) / ly);
 }
 
