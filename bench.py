@@ -241,16 +241,28 @@ def cpu_baseline(wl, target_s=10.0):
         n += 1
     dt = time.perf_counter() - t0
     nodes = wl["nx"] * wl["ny"]
+    # the same oracle on one thread (a few whole-grid steps)
+    threads = lb_oracle.num_threads()
+    lb_oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t1 < target_s / 2:
+        g.step(1)
+        n1 += 1
+    dt1 = time.perf_counter() - t1
+    lb_oracle.set_num_threads(threads)
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
             model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": lb_oracle.num_threads(),
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle", "cpu_model": model,
+            "single_thread_MLUPS": round(nodes * n1 / dt1 / 1e6, 2), "single_thread_steps": n1,
             "sample": "%d whole-grid steps of the 4096x4096 layered D2Q5 BGK workload "
-                      "(FP64, C loops, OpenMP over rows), %.1f s" % (n, dt)}
+                      "(FP64, C loops, OpenMP over rows), %.1f s; then %d steps on one thread, %.1f s"
+                      % (n, dt, n1, dt1)}
 
 
 def pulse_variant(torch, lbwave, inputs):
@@ -316,9 +328,12 @@ def main():
     cap = steps + warmup + 1
 
     nsl = max_steps_per_launch(lbwave, 5, "bgk", "f32")
-    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + nsl * 501 + 10)
+    grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + 2 * steps + nsl * 501 + 10)
     log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
     t = time_steps(torch, grid, steps, warmup)
+    # two more windows of the same steps, reported beside the first (which
+    # gives `value`) with the median of the three
+    windows = [t] + [time_steps(torch, grid, steps, 0) for _ in range(2)]
     mlups = N * steps / t / 1e6
     plan = launch_plan(steps, nsl)
     # the blocked kernel's launch duration: two calls that differ only in
@@ -390,6 +405,8 @@ def main():
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(t / steps * 1e3, 5),
+        "ms_per_step_windows": [round(w / steps * 1e3, 5) for w in windows],
+        "ms_per_step_median3": round(sorted(windows)[1] / steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "layered two-layer medium + 20 anomalies, 4096x4096 "

@@ -177,3 +177,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the OpenMP threads of later steps (timing only: the result of a step
+   does not depend on it, each node being written by one thread). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -133,6 +133,8 @@ def _lib():
         lib.orc_node_weights.restype = None
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_num_threads.restype = None
         _LIB = lib
     return _LIB
 
@@ -145,6 +147,11 @@ def _dptr(a):
 def num_threads():
     """OpenMP threads the C step runs on."""
     return int(_lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of later C steps (for timing; results do not depend on it)."""
+    _lib().orc_set_num_threads(int(n))
 
 
 class OracleGrid:
