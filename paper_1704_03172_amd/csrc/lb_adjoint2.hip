@@ -60,6 +60,10 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
     int xw[V], dxw[V];
     bool own[V];
     const bool own_lane = lane >= H && lane < 64 - H;
+    // whether any column of the strip lies within the sponge width of a side
+    // edge: else the sponge depends on the row alone
+    const int L = p.sponge_width;
+    const bool strip_sponge = sx * OW - H * V < L || sx * OW - H * V + 64 * V - 1 >= nx - L;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         xw[j] = wrapi(xl + j, nx);
@@ -118,6 +122,25 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
         auto &A = st == 1 ? L0 : L1;
         T mu[Q][V];
         pull_back_row<T, Q, V>(A[m - 1], A[m], A[m + 1], mu);
+        // the sponge factor (1 - sigma) on mu: one wave-uniform test per row,
+        // the per-node multiply (as adjoint_node's) only in rows that reach it
+        const int dy = min(wm, ny - 1 - wm);
+        if (strip_sponge || dy < L) {
+            asm volatile("");
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int d = min(dxw[j], dy);
+                if (d < L) {
+                    asm volatile("");
+                    T mj[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) mj[i] = mu[i][j];
+                    apply_sponge<T, Q>(d, L, p.sponge_smax, mj);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) mu[i][j] = mj[i];
+                }
+            }
+        }
         const int rb = __builtin_amdgcn_readlane(rb_l, m - 1), re = __builtin_amdgcn_readlane(re_l, m - 1);
         const int64_t col = st == 1 ? p.rec.col : p.rec.col - 1;
         const double sn = st == 1 ? p.s_n : p.s_prev;
@@ -132,8 +155,8 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
             if constexpr (m >= 2 && m - 2 < LY) {
                 if (owned_row) rho = st == 1 ? R1[m - 2][j] : R2[m - 2][j];
             }
-            const double g = adjoint_node<T, Q, KIND>(p, muj, C[m][j], rho, xw[j], wm, min(dxw[j], min(wm, ny - 1 - wm)),
-                                                      rb, re, col, sn, initial, lam);
+            const double g = adjoint_node<T, Q, KIND>(p, muj, C[m][j], rho, xw[j], wm, min(dxw[j], dy), rb, re, col, sn,
+                                                      initial, lam, false);
             if constexpr (m >= 2 && m - 2 < LY) {
                 if (owned_row && own[j]) G[m - 2][j] += g;
             }

@@ -340,12 +340,14 @@ __device__ inline void post_node(const StepParams &p, const T (&g)[Q], T c2, int
 // so both give the same bits.
 template <typename T, int Q, int KIND>
 __device__ inline double adjoint_node(const AdjointParams &p, const T (&mu)[Q], T c2, T rho, int x, int y, int dedge,
-                                      int rb, int re, int64_t col, double s_n, bool initial, T (&lam)[Q]) {
+                                      int rb, int re, int64_t col, double s_n, bool initial, T (&lam)[Q],
+                                      bool sponge = true) {
     const T *res = reinterpret_cast<const T *>(p.rec.traces);
     T m[Q], nu[Q], w[Q];
     // (1 - sigma) P^T lambda: outside the sponge the factor is 1 and
-    // mu * 1 = mu, so only nodes inside it multiply
-    if (dedge < p.sponge_width) {
+    // mu * 1 = mu, so only nodes inside it multiply (sponge false: the
+    // caller has applied the factor to mu already)
+    if (sponge && dedge < p.sponge_width) {
         asm volatile("");
         const T sf = sponge_at<T>(dedge, p.sponge_width, p.sponge_smax);
 #pragma unroll
@@ -389,7 +391,10 @@ __device__ inline double adjoint_node(const AdjointParams &p, const T (&mu)[Q], 
             dm += p.dw[i] * double(m[i]);
         }
         gacc += double(rho) * dn;
-        if (y == p.src_y && x == p.src_x) gacc += s_n * dm;
+        if (y == p.src_y) {   // uniform over a row: only the source row tests x
+            asm volatile("");
+            if (x == p.src_x) gacc += s_n * dm;
+        }
     }
     weights<T, Q>(c2, p.coll, w);
     T s0 = T(0), sxv = T(0), syv = T(0);
