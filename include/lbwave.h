@@ -109,9 +109,9 @@ typedef struct lb_grid lb_grid;
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
  *   steps_per_launch  0 (default): lb_step_n advances several time steps
  *                  per kernel launch (temporal blocking: four for D2Q5 and
- *                  for D2Q9 with FP64 populations, three for D2Q9 BGK and
- *                  two for D2Q9 MRT with FP32 populations, three for D2Q5
- *                  and one for D2Q9 with FP16 storage; lb_blocked_steps reports
+ *                  for D2Q9 with FP64 populations, three for D2Q9 with FP32
+ *                  populations, three for D2Q5 and one for D2Q9 with FP16
+ *                  storage; lb_blocked_steps reports
  *                  the count) wherever it can (no patch, no sum-rho
  *                  recording, no checkpoint falling inside a launch; the
  *                  last launch of each call takes one step), which divides

@@ -188,7 +188,7 @@ __device__ inline A &pick4(A &a0, A &a1, A &a2, A &a3) {
 template <typename S, int Q, int KIND>
 constexpr int tn_max() {
     if constexpr (sizeof(S) == 2) return Q == 5 ? 3 : 1;
-    else if constexpr (Q == 9 && sizeof(S) == 4) return KIND == 1 ? 2 : 3;
+    else if constexpr (Q == 9 && sizeof(S) == 4) return 3;
     else return 4;
 }
 
@@ -201,11 +201,13 @@ constexpr int tn_max() {
 // (at most 168 VGPRs) where it was there before (D2Q5 FP32 6 rows: 9 %
 // faster than 4, 7 rows within 0.1 % for BGK at tau = 1/2 and 8 rows no
 // faster; D2Q9 FP32 BGK 5 rows: 7 % faster than 4, 3 rows at three waves
-// per SIMD 2.5 % slower; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows:
-// 10 %; FP16 storage 5 rows with three steps: 3 %).
+// per SIMD 2.5 % slower; D2Q9 FP32 MRT three steps in 3-row segments, three
+// waves per SIMD: 21 % faster than two steps in 4 rows, 4 rows at two waves
+// 12 % slower; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows: 10 %; FP16
+// storage 5 rows with three steps: 3 %).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
-    if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 4) : sizeof(S) == 8 ? 6 : 5;
+    if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 3) : sizeof(S) == 8 ? 6 : 5;
     else if constexpr (sizeof(S) == 2) return 5;
     else if constexpr (NS == 4) return 6;
     else if constexpr (NS == 2 && sizeof(S) == 4) return 8;

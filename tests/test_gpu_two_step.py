@@ -38,14 +38,14 @@ def both(case, precision, spl=0, **kw):
 
 def boundary_receivers(nx, ny):
     """Receivers on the strip edges of every storage format (owned widths
-    120 for FP32, 56 for FP64, 224 for FP16 storage), on 4-, 5-, 6- and 8-row
-    segment edges and on the periodic seam."""
+    120 for FP32, 56 for FP64, 224 for FP16 storage), on 3-, 4-, 5-, 6- and
+    8-row segment edges and on the periodic seam."""
     xs = {0, 1, nx - 1, nx - 2}
     for w in (56, 120, 224):
         for k in range(1, nx // w + 1):
             xs.update({k * w - 1, k * w, k * w + 1})
     ys = {0, 1, ny - 1, ny - 2}
-    for h in (4, 5, 6, 8):
+    for h in (3, 4, 5, 6, 8):
         for k in range(1, ny // h + 1):
             ys.update({h * k - 1, h * k})
     xs = sorted(x for x in xs if 0 <= x < nx)
@@ -143,14 +143,15 @@ def test_segment_edges(ny):
     (6 rows), D2Q5 FP32 with three (6 rows) and two (8 rows), D2Q5 FP64 MRT
     with four (6 rows), D2Q5 FP16 storage with three (5 rows), D2Q9 BGK FP32
     with three (5 rows), D2Q9 BGK FP64 with four (6 rows), D2Q9 MRT FP32
-    with two (4 rows) and D2Q9 MRT FP64 with four (5 rows), so that every
+    with three (3 rows) and two (3 rows) and D2Q9 MRT FP64 with four (5
+    rows), so that every
     direction crosses the segment edges."""
     mrt9 = [1, 1, 1, 2, 2, 2, 1, 1, 2]
     mrt5 = [1, 1, 1, 1.6, 1.3]
     for q, coll, s, prec, spl in ((5, "bgk", None, "f32", 0), (5, "mrt", mrt5, "f32", 0), (5, "bgk", None, "f32", 3),
                                   (5, "bgk", None, "f32", 2), (5, "mrt", mrt5, "f64", 0), (5, "bgk", None, "f16s", 0),
                                   (9, "bgk", None, "f32", 0), (9, "bgk", None, "f64", 0), (9, "mrt", mrt9, "f32", 0),
-                                  (9, "mrt", mrt9, "f64", 0)):
+                                  (9, "mrt", mrt9, "f32", 2), (9, "mrt", mrt9, "f64", 0)):
         case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2 if ny > 4 else 0)
         case["receivers"] = np.concatenate([case["receivers"], boundary_receivers(300, ny)])
         two = both(case, prec, spl=spl)
