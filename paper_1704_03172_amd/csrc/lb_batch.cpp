@@ -126,7 +126,7 @@ int rebuild(lb_batch *b) {
         const ShotEntry &e = b->table[(size_t)k];
         b->order.push_back(k);
         b->prefix.push_back(b->prefix.back() + (int64_t)e.bx * e.ny);
-        if (b->ns > 1) b->wprefix.push_back(b->wprefix.back() + lbw::stepn_waves(b->storage, b->q, b->coll.kind, b->ns, e.nx, e.ny));
+        if (b->ns > 1) b->wprefix.push_back(b->wprefix.back() + lbw::stepn_waves(b->storage, b->q, lbw::step_kind(b->coll), b->ns, e.nx, e.ny));
     }
     b->total_blocks = b->prefix.back();
     b->total_waves = b->ns > 1 ? b->wprefix.back() : 0;

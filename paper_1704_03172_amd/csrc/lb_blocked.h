@@ -204,11 +204,12 @@ constexpr int tn_max() {
 // per SIMD 2.5 % slower; D2Q9 FP32 MRT three steps in 3-row segments, three
 // waves per SIMD: 21 % faster than two steps in 4 rows, 4 rows at two waves
 // 12 % slower; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows: 10 %; FP16
-// storage 5 rows with three steps: 3 %).
+// storage with three steps: BGK at tau = 1/2 5 rows, 3 % faster than 4;
+// MRT and general BGK 4 rows, three waves per SIMD, 11 % faster than 5).
 template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
     if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 3) : sizeof(S) == 8 ? 6 : 5;
-    else if constexpr (sizeof(S) == 2) return 5;
+    else if constexpr (sizeof(S) == 2) return KIND == 2 ? 5 : 4;
     else if constexpr (NS == 4) return 6;
     else if constexpr (NS == 2 && sizeof(S) == 4) return 8;
     else if constexpr (NS == 3) return 6;
@@ -518,12 +519,14 @@ hipError_t by_steps(int ns, F &&f) {
     return hipErrorInvalidValue;
 }
 
+// Waves of an NS-step launch over an nx x ny grid; kind is the kernel's
+// collision kind (step_kind: 0, 1 or 2), whose segment height it takes.
 template <typename S, int Q>
 int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
     int ly = 1;
     const hipError_t e = by_steps<S, Q>(ns, [&](auto nc) {
         constexpr int NS = decltype(nc)::value;
-        ly = kind == 1 ? tn_rows<S, Q, NS, 1>() : tn_rows<S, Q, NS, 0>();
+        ly = kind == 1 ? tn_rows<S, Q, NS, 1>() : kind == 2 ? tn_rows<S, Q, NS, 2>() : tn_rows<S, Q, NS, 0>();
         return hipSuccess;
     });
     if (e != hipSuccess) return 0;   // a step count without a kernel: no waves
@@ -533,10 +536,10 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
 // The single-grid NS-step launch for storage S and lattice Q.
 template <typename S, int Q>
 hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
-    const dim3 grid((unsigned)((waves_of<S, Q>(p.coll.kind, ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const int kind = step_kind(p.coll);
+    const dim3 grid((unsigned)((waves_of<S, Q>(kind, ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
     // vector accesses need every lane's columns contiguous after the wrap
     const bool vec = p.nx % Tb<S>::V == 0;
-    const int kind = step_kind(p.coll);
     return by_steps<S, Q>(ns, [&](auto nc) {
         constexpr int NS = decltype(nc)::value;
         auto launch = [&](auto kc) {

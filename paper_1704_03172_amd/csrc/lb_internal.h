@@ -208,7 +208,7 @@ hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact
 // Blocked batch launch with the ns-step kernel: every active shot advances
 // min(ns, bp.max_run, steps left) steps; then launch_batch_advance_n with
 // run = bp.max_run.  nwaves: sum of stepn_waves over the active shots.
-int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny);   // kind: Collision::kind
+int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny);   // kind: step_kind()
 hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp, int64_t nwaves, hipStream_t s);
 hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,

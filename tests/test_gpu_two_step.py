@@ -141,7 +141,8 @@ def test_segment_edges(ny):
     grids shorter than the halo): D2Q5 FP32 BGK with four steps (6-row
     segments, rows loaded six ahead of the walk), D2Q5 FP32 MRT with four
     (6 rows), D2Q5 FP32 with three (6 rows) and two (8 rows), D2Q5 FP64 MRT
-    with four (6 rows), D2Q5 FP16 storage with three (5 rows), D2Q9 BGK FP32
+    with four (6 rows), D2Q5 FP16 storage with three (5 rows for BGK at
+    tau = 1/2, 4 for MRT), D2Q9 BGK FP32
     with three (5 rows), D2Q9 BGK FP64 with four (6 rows), D2Q9 MRT FP32
     with three (3 rows) and two (3 rows) and D2Q9 MRT FP64 with four (5
     rows), so that every
@@ -150,6 +151,7 @@ def test_segment_edges(ny):
     mrt5 = [1, 1, 1, 1.6, 1.3]
     for q, coll, s, prec, spl in ((5, "bgk", None, "f32", 0), (5, "mrt", mrt5, "f32", 0), (5, "bgk", None, "f32", 3),
                                   (5, "bgk", None, "f32", 2), (5, "mrt", mrt5, "f64", 0), (5, "bgk", None, "f16s", 0),
+                                  (5, "mrt", mrt5, "f16s", 0),
                                   (9, "bgk", None, "f32", 0), (9, "bgk", None, "f64", 0), (9, "mrt", mrt9, "f32", 0),
                                   (9, "mrt", mrt9, "f32", 2), (9, "mrt", mrt9, "f64", 0)):
         case = layered_case(300, ny, q=q, collision=coll, s=s, nsteps=40, sponge=2 if ny > 4 else 0)
