@@ -200,7 +200,8 @@ constexpr int tn_max() {
 // measured faster at 4096^2 while the kernel stays at three waves per SIMD
 // (at most 168 VGPRs) where it was there before (D2Q5 FP32 6 rows: 9 %
 // faster than 4, 7 rows within 0.1 % for BGK at tau = 1/2 and 8 rows no
-// faster; D2Q9 FP32 BGK 5 rows: 7 % faster than 4, 3 rows at three waves
+// faster; D2Q5 FP64 7 rows 2 % faster than 6 (8: MRT at two waves);
+// D2Q9 FP32 BGK 5 rows: 7 % faster than 4, 3 rows at three waves
 // per SIMD 2.5 % slower; D2Q9 FP32 MRT three steps in 3-row segments, three
 // waves per SIMD: 21 % faster than two steps in 4 rows, 4 rows at two waves
 // 12 % slower; D2Q9 FP64 BGK 6 rows: 8 %; D2Q9 FP64 MRT 5 rows: 10 %; FP16
@@ -210,7 +211,7 @@ template <typename S, int Q, int NS, int KIND>
 constexpr int tn_rows() {
     if constexpr (Q == 9) return KIND == 1 ? (sizeof(S) == 8 ? 5 : 3) : sizeof(S) == 8 ? 6 : 5;
     else if constexpr (sizeof(S) == 2) return KIND == 2 ? 5 : 4;
-    else if constexpr (NS == 4) return 6;
+    else if constexpr (NS == 4) return sizeof(S) == 8 ? 7 : 6;
     else if constexpr (NS == 2 && sizeof(S) == 4) return 8;
     else if constexpr (NS == 3) return 6;
     else return 4;

@@ -38,14 +38,14 @@ def both(case, precision, spl=0, **kw):
 
 def boundary_receivers(nx, ny):
     """Receivers on the strip edges of every storage format (owned widths
-    120 for FP32, 56 for FP64, 224 for FP16 storage), on 3-, 4-, 5-, 6- and
-    8-row segment edges and on the periodic seam."""
+    120 for FP32, 56 for FP64, 224 for FP16 storage), on 3-, 4-, 5-, 6-, 7-
+    and 8-row segment edges and on the periodic seam."""
     xs = {0, 1, nx - 1, nx - 2}
     for w in (56, 120, 224):
         for k in range(1, nx // w + 1):
             xs.update({k * w - 1, k * w, k * w + 1})
     ys = {0, 1, ny - 1, ny - 2}
-    for h in (3, 4, 5, 6, 8):
+    for h in (3, 4, 5, 6, 7, 8):
         for k in range(1, ny // h + 1):
             ys.update({h * k - 1, h * k})
     xs = sorted(x for x in xs if 0 <= x < nx)
@@ -141,7 +141,7 @@ def test_segment_edges(ny):
     grids shorter than the halo): D2Q5 FP32 BGK with four steps (6-row
     segments, rows loaded six ahead of the walk), D2Q5 FP32 MRT with four
     (6 rows), D2Q5 FP32 with three (6 rows) and two (8 rows), D2Q5 FP64 MRT
-    with four (6 rows), D2Q5 FP16 storage with three (5 rows for BGK at
+    with four (7 rows), D2Q5 FP16 storage with three (5 rows for BGK at
     tau = 1/2, 4 for MRT), D2Q9 BGK FP32
     with three (5 rows), D2Q9 BGK FP64 with four (6 rows), D2Q9 MRT FP32
     with three (3 rows) and two (3 rows) and D2Q9 MRT FP64 with four (5
