@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the method's per-GPU share is the single-GPU kernel); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
