@@ -219,7 +219,11 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum);
 
 /* Enqueue n time steps (coarse steps with a patch) on the bound stream and
  * return.  The first call after lb_set_state also performs the collision of
- * time 0.  Each step is one fused pull-stream + collide launch. */
+ * time 0.  Every launch fuses pull-stream, collision, source, sponge and
+ * recording; a launch takes up to lb_blocked_steps() steps (see
+ * steps_per_launch), and the last launch of each call takes one.  A coarse
+ * step of a patch takes three launches (the coarse step with the interface
+ * work, then the two fine sub-steps). */
 int lb_step_n(lb_grid *h, int64_t n);
 
 /* Current time n of the handle (pre-collision state at time n). */

@@ -27,11 +27,15 @@ reading implemented here (bidirectional two-line exchange) is:
     node that receives the value (eq. coarse-fine dist connect);
   * at time 0 the same two overwrites are applied once to the initial state.
 
-Parity status: R_f and the schedule are pinned by properties (R_f keeps rho
-and J, R_2 o R_1/2 = identity, a homogeneous medium shows only a small
-spurious reflection at the interface, and removing the rescaling makes it
-markedly larger); beyond that the composite is parity unpinned except
-against the GPU path.
+Pins (tests/test_oracle_refine.py): R_f keeps rho and J and R_2 o R_1/2 is
+the identity; the fine ring reproduces a bicubic coarse state exactly (the
+4-point interpolant's exactness) and, at the intermediate time, a state
+linear in time exactly (the temporal mean's exactness); the restriction
+copies the coincident fine nodes to the coarse inner ring and nothing else;
+planted mistakes (linear weights, a shifted stencil, no temporal mean) fail
+those pins; a wide pulse in a homogeneous medium shows a spurious interface
+signal below 1e-3 of the recorded one, and at least ten times more without
+the rescaling; a uniform pressure at rest stays exact.
 """
 import numpy as np
 

@@ -321,11 +321,26 @@ class Grid:
     def set_raw_state(self, blob):
         _check(lib().lb_set_raw_state(self.handle, ctypes.c_void_p(blob.data_ptr())), "lb_set_raw_state")
 
+    def _trace_shaped(self, a, name):
+        """a as a contiguous device tensor [nrec][trace_capacity] of the
+        arithmetic type; ValueError (before any launch) for any other shape,
+        since the kernels index it as r * trace_capacity + n."""
+        torch = self._torch
+        if self.traces is None:
+            raise ValueError("%s: no receivers recorded" % name)
+        nrec = int(self.traces.shape[1])
+        shape = tuple(a.shape)
+        if shape not in ((nrec, self.trace_capacity), (1, nrec, self.trace_capacity)):
+            raise ValueError("%s must have shape (%d, %d) = (nrec, trace_capacity), got %s"
+                             % (name, nrec, self.trace_capacity, shape))
+        return torch.as_tensor(a).to(device=self.device, dtype=self.dtype).reshape(
+            nrec, self.trace_capacity).contiguous()
+
     def misfit(self, d_obs, nt):
         """(phi, residual) of the recorded pressure traces against d_obs
         [nrec][trace_capacity] (device tensor of the arithmetic type)."""
         torch = self._torch
-        d_obs = d_obs.to(device=self.device, dtype=self.dtype).contiguous()
+        d_obs = self._trace_shaped(d_obs, "d_obs")
         res = torch.zeros_like(d_obs)
         phi = torch.zeros((), dtype=torch.float64, device=self.device)
         _check(lib().lb_misfit(self.handle, ctypes.c_void_p(d_obs.data_ptr()), int(nt),
@@ -336,7 +351,7 @@ class Grid:
         """dL/dc^2 [ny][nx] (FP64) for trace sensitivities res
         [nrec][trace_capacity] after a forward run of nt steps."""
         torch = self._torch
-        res = res.to(device=self.device, dtype=self.dtype).contiguous()
+        res = self._trace_shaped(res, "res")
         grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
         _check(lib().lb_adjoint(self.handle, ctypes.c_void_p(res.data_ptr()), int(nt),
                                 ctypes.c_void_p(grad.data_ptr())), "lb_adjoint")

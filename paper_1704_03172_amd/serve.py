@@ -5,12 +5,14 @@ receivers, step count) arrive over time.  The server keeps every admitted
 shot's state resident in HBM, admits new shots whenever a slot and the memory
 budget allow (footprint = the shot workspace reported by the library plus its
 trace buffer), and advances all active shots together: each tick is k time
-steps of one batched launch per step, replayed from a captured HIP graph.  A
-shot that reaches its last step stops updating inside the tick; at the end of
-the tick its traces are copied out and its slot and memory are freed.
+steps in batched launches of several steps each (as lb_blocked_steps gives),
+replayed from a captured HIP graph.  A shot that reaches its last step stops
+updating inside the tick; once the tick has run, its traces are copied out
+and its slot and memory are freed.
 
 run_fifo() is the baseline on the same trace: one shot at a time, in arrival
-order, one launch per step (the single-grid lb_step_n path).
+order, through the single-grid lb_step_n path (several steps per launch, one
+shot per launch).
 
 Latency of a request = completion - arrival = queue wait + service.
 """

@@ -157,3 +157,38 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lbwave, "_LIB", None)
     with pytest.raises(RuntimeError):
         lbwave.lib()
+
+
+def test_trace_shaped_arrays_are_checked_before_any_launch(lw):
+    """Grid.misfit and Grid.adjoint take [nrec][trace_capacity] arrays that
+    the kernels index as r * trace_capacity + n; any other shape must raise
+    ValueError on the host before the library is called."""
+    import torch
+
+    class NoLib:
+        def __getattr__(self, name):
+            raise AssertionError("library called with a mis-shaped array: " + name)
+
+    g = object.__new__(lw.Grid)
+    g._torch = torch
+    g.device = torch.device("cpu")
+    g.dtype = torch.float32
+    g.trace_capacity = 11
+    g.traces = torch.zeros((1, 3, 11))
+    g._h = ctypes.c_void_p(1)
+    saved = lw._LIB
+    lw._LIB = NoLib()
+    try:
+        for bad in ((3, 10), (3, 12), (2, 11), (33,), (1, 3, 10), (2, 3, 11)):
+            with pytest.raises(ValueError):
+                g.misfit(torch.zeros(bad), 10)
+            with pytest.raises(ValueError):
+                g.adjoint(torch.zeros(bad), 10)
+        ok = g._trace_shaped(torch.arange(33.0).reshape(1, 3, 11), "d_obs")
+        assert tuple(ok.shape) == (3, 11) and float(ok[2, 10]) == 32.0
+        g.traces = None
+        with pytest.raises(ValueError):
+            g.misfit(torch.zeros((3, 11)), 10)
+    finally:
+        lw._LIB = saved
+        g._h = None
