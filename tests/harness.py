@@ -65,11 +65,12 @@ def make_grid(case, precision, steps_per_launch=0):
                        steps_per_launch=steps_per_launch, **extra)
 
 
-def run_gpu(case, precision="f32", chunks=None, on_device=False, sum_rho=True, steps_per_launch=0):
+def run_gpu(case, precision="f32", chunks=None, on_device=False, sum_rho=False, steps_per_launch=0):
     """Run the case through the C-ABI.  chunks: list of step counts whose sum
-    is nsteps (exercises repeated lb_step_n calls).  Recording the sum of rho
-    keeps lb_step_n at one step per launch; sum_rho=False lets it take two
-    steps per launch (unless steps_per_launch=1)."""
+    is nsteps (exercises repeated lb_step_n calls).  By default lb_step_n
+    takes as many steps per launch as the blocked kernel offers (the path
+    the benchmark times); recording the sum of rho (sum_rho=True) or
+    steps_per_launch=1 keeps it at one step per launch."""
     import torch
     grid = make_grid(case, precision, steps_per_launch)
     ny, nx = case["ny"], case["nx"]

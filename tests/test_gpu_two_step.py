@@ -106,7 +106,7 @@ def test_two_step_shapes(precision, nx, ny):
                 "receivers": np.concatenate([np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2)],
                                                       dtype=np.int32), boundary_receivers(nx, ny)])}
         two = both(case, precision)
-        compare(case, precision, gpu=two)
+        compare(case, precision, gpu=two, j_floor=True)
 
 
 # source nodes on strip edges (owned widths 120, 56 and 224), on 5-, 6- and
