@@ -31,7 +31,10 @@ struct Collision {
     int32_t kind = 0;                  // LB_BGK or LB_MRT
     double omega = 2.0;                // BGK 1/tau
     double srate[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double kax = 0.5, kdg = 0.0;       // w_i / c^2 for axis / diagonal movers
+    double kax = 0.5, kdg = 0.0;       // w_i / c^2 for axis / diagonal movers in the
+                                       // equilibrium's J term (2 kax + 4 kdg = 1 exactly
+                                       // in the arithmetic type)
+    double kw = 0.5;                   // D2Q9 weights: w1 = c^2 kw, kw = 1 / (2 + 4r)
     double ratio = 0.0;                // D2Q9 w5 / w1
 };
 

@@ -1061,6 +1061,44 @@ namespace lbw {
 static const double kNormD2Q5[5] = {5, 2, 2, 20, 4};
 static const double kNormD2Q9[9] = {9, 6, 6, 36, 4, 36, 12, 12, 4};
 
+// The D2Q9 equilibrium's momentum coefficients w_i / c^2 (kax for the axis
+// movers, kdg for the diagonal ones) as numbers of the arithmetic type with
+// 2 kax + 4 kdg = 1 exactly, so that sum_i c_i g^eq_i is J with no bias
+// (eq. linear eqm dist; the identity is sum_i w_i c_i c_i = c^2 I of eq. LB
+// lattice moments).  Rounded to nearest on their own, 1/3 and 1/12 give
+// 2 kax + 4 kdg = 1 + 3e-8 in FP32; at omega = 2 the collision then
+// multiplies J by 1 + 6e-8 every step, a drift that grows linearly in time
+// (measured: 8e-5 of rho after 2000 steps of the 1024^2 layered workload).
+// kdg is moved by the fewest units in the last place that make 1 - 4 kdg
+// halve into a representable kax.  For large ratios kax is then off
+// 1 / (2 + 4r) by up to ~1e-5 relative (it is small beside 4 kdg ~ 1), which
+// is why the weights take their own coefficient kw: the axis movers carry a
+// share 2 kax ~ 1 / (1 + 2r) of the momentum, so the J term's change is
+// below 1e-7 of J.
+template <typename F>
+static void momentum_exact_pair(double ratio, double *kax, double *kdg) {
+    const F d0 = F(ratio / (2.0 + 4.0 * ratio));
+    for (int m = 0; m <= 16; ++m) {
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            F d = d0;
+            for (int k = 0; k < m; ++k) d = std::nextafter(d, sgn < 0 ? F(0) : F(1));
+            // t = 1 - 4d, checked for exactness with an FMA (1 - t is exact
+            // for t in [1/2, 1])
+            const F t = F(1) - F(4) * d;
+            if (std::fma(F(-4), d, F(1) - t) != F(0)) continue;
+            const F a = t / F(2);
+            if (F(2) * a == t && F(2) * a + F(4) * d == F(1)) {
+                *kax = double(a);
+                *kdg = double(d);
+                return;
+            }
+            if (m == 0) break;
+        }
+    }
+    *kax = 1.0 / (2.0 + 4.0 * ratio);   // not reached for ratios in use
+    *kdg = ratio / (2.0 + 4.0 * ratio);
+}
+
 Collision make_collision(const lb_grid_desc *d) {
     Collision c;
     c.kind = d->collision;
@@ -1068,8 +1106,13 @@ Collision make_collision(const lb_grid_desc *d) {
     const double *norm = d->lattice == LB_D2Q5 ? kNormD2Q5 : kNormD2Q9;
     for (int k = 0; k < 9; ++k) c.srate[k] = (k >= 3 && k < d->lattice) ? d->s[k] / norm[k] : 0.0;
     c.ratio = d->lattice == LB_D2Q9 ? d->d2q9_ratio : 0.0;
-    c.kax = d->lattice == LB_D2Q9 ? 1.0 / (2.0 + 4.0 * c.ratio) : 0.5;
-    c.kdg = d->lattice == LB_D2Q9 ? c.ratio / (2.0 + 4.0 * c.ratio) : 0.0;
+    c.kax = 0.5;
+    c.kdg = 0.0;
+    c.kw = d->lattice == LB_D2Q9 ? 1.0 / (2.0 + 4.0 * c.ratio) : 0.5;
+    if (d->lattice == LB_D2Q9) {
+        if (d->precision == LB_F64) momentum_exact_pair<double>(c.ratio, &c.kax, &c.kdg);
+        else momentum_exact_pair<float>(c.ratio, &c.kax, &c.kdg);
+    }
     return c;
 }
 
