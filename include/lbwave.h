@@ -244,11 +244,38 @@ int lb_set_raw_state(lb_grid *h, const void *d_in);
 
 /* Misfit of the recorded pressure traces against observed data:
  * res = p - d_obs and phi = 1/2 sum_r sum_{n <= nt} res^2 (FP64, fixed
- * summation order).  d_obs and d_res are device arrays [nrec][trace_capacity]
+ * summation order: block partials reduced by wave64 shuffles, then one
+ * block adding them in order; the partials live in the grid's workspace).  d_obs and d_res are device arrays [nrec][trace_capacity]
  * of the arithmetic type (columns 0..nt used); d_phi one device double.
  * Needs receivers recorded with LB_FIELD_P. */
 int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res,
               double *d_phi);
+
+/* Device workspace bytes lb_trace_misfit needs: FP64 partial sums of at
+ * most 2048 blocks. */
+#define LB_TRACE_MISFIT_WORKSPACE_BYTES 16384
+
+/* The misfit of lb_misfit for trace arrays that no grid handle owns (for
+ * instance the traces of shots run by the batched executor):
+ * res = traces - obs and phi = 1/2 sum_r sum_{n < ncols} res^2.
+ *   d_traces, d_obs, d_res  device arrays [nrec][cap] of the arithmetic type
+ *                  (float for LB_F32 and LB_F16S, double for LB_F64);
+ *                  columns 0 .. ncols-1 of each row are read / written.
+ *   d_phi          one device double (FP64 sum in a fixed order: the result
+ *                  is reproducible bit for bit).
+ *   d_workspace    caller-owned device scratch of ws_bytes >=
+ *                  LB_TRACE_MISFIT_WORKSPACE_BYTES, 8-byte aligned, for the
+ *                  block partials; it must stay untouched until the stream
+ *                  has run the call.
+ * The reduction takes one partial per block of a grid-stride loop (at most
+ * 2048 blocks), wave64 shuffles inside each block, and one block that adds
+ * the partials in order.  Enqueued on `stream`; returns without waiting.
+ * LB_E_INVALID for NULL pointers or another dtype, LB_E_RANGE unless
+ * nrec >= 1 and 1 <= ncols <= cap (and nrec x cap fits int64),
+ * LB_E_WORKSPACE for a missing, small or misaligned workspace, LB_E_HIP if
+ * the launch fails. */
+int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_t nrec, int64_t cap,
+                    int64_t ncols, lb_dtype t, double *d_phi, void *d_workspace, size_t ws_bytes, void *stream);
 
 /* Gradient of a trace misfit with respect to the per-node c^2 by the
  * discrete adjoint of the scheme (the paper's update differentiated exactly:

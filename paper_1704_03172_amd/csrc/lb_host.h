@@ -29,6 +29,11 @@ inline double c2_max(int lattice, double ratio) {
 // norms |M_k|^2 of the moment matrices of Appendix A).
 Collision make_collision(const lb_grid_desc *d);
 
+// Argument checks shared by the trace-misfit entry points (lb_trace_misfit
+// and its variant without workspace): LB_OK, LB_E_INVALID or LB_E_RANGE.
+int check_trace_misfit(const void *traces, const void *obs, const void *res, int32_t nrec, int64_t cap,
+                       int64_t ncols, lb_dtype t, const double *phi);
+
 // Validate the scheme part of a descriptor (lattice, collision, precision,
 // rates, D2Q9 ratio).
 int validate_scheme(const lb_grid_desc *d);

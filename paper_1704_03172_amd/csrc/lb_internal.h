@@ -202,8 +202,14 @@ hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s);
 // lambda(n+1) from p.lam_next, lambda(n-1) to p.lam, rho(n) in p.rho and
 // rho(n-1) in p.rho_prev; the gradient gets the terms of n, then of n - 1.
 hipError_t launch_adjoint2(int storage, const AdjointParams &p, hipStream_t s);
+// Trace misfit: res = traces - obs over columns 0 .. ncols-1 of nrec rows of
+// cap columns, and phi = 1/2 sum res^2 (FP64) through misfit_blocks(nrec,
+// ncols) block partials in `partial` (at most kMisfitMaxBlocks doubles), then
+// one finalize block; the result depends only on the inputs (fixed order).
+constexpr int kMisfitMaxBlocks = 2048;
+int misfit_blocks(int32_t nrec, int64_t ncols);
 hipError_t launch_misfit(int storage, const void *traces, const void *obs, void *res, int32_t nrec,
-                         int64_t cap, int64_t ncols, double *phi, hipStream_t s);
+                         int64_t cap, int64_t ncols, double *phi, double *partial, hipStream_t s);
 int step_vwidth(int storage);
 int step_tile_nodes(int storage);   // x-nodes covered by one step block
 hipError_t launch_step_batch(int storage, int q, const BatchParams &bp, int64_t nblocks, hipStream_t s);

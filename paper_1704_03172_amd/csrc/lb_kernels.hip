@@ -468,28 +468,53 @@ __global__ __launch_bounds__(kStepBlock) void k_adjoint(AdjointParams p) {
     for (int i = 0; i < Q; ++i) store_x<T, V>(lo + i * p.pstride + (int64_t)y * nx, x0, nx, outv[i]);
 }
 
-// Residual r = p - d and misfit phi = 1/2 sum r^2 over columns 0 .. ncols-1
-// of every receiver (one block, fixed summation order: deterministic).
+// Sum of a value over the 64 lanes of a wavefront by shuffles (lane 0 gets
+// it); the order of the additions is fixed, so the result is reproducible.
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over a block of kBlock threads: wave sums, then the wave partials in
+// wave order (thread 0 gets it).
+__device__ inline double block_sum(double v) {
+    __shared__ double sh[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w];
+    }
+    return s;
+}
+
+// Residual r = p - d over columns 0 .. ncols-1 of every receiver (written
+// to res) and the per-block partial sums of r^2 in FP64 (partial[b], one per
+// block of a grid-stride loop over the nrec x ncols elements).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_misfit(const T *traces, const T *obs, T *res, int32_t nrec, int64_t cap,
-                                                   int64_t ncols, double *phi) {
+__global__ __launch_bounds__(kBlock) void k_misfit_partial(const T *traces, const T *obs, T *res, int32_t nrec,
+                                                           int64_t cap, int64_t ncols, double *partial) {
     double s = 0.0;
     const int64_t n = (int64_t)nrec * ncols;
-    for (int64_t k = threadIdx.x; k < n; k += kBlock) {
-        const int64_t r = k / ncols, c = k % ncols;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t r = k / ncols, c = k - r * ncols;
         const int64_t idx = r * cap + c;
         const T d = traces[idx] - obs[idx];
         res[idx] = d;
         s += double(d) * double(d);
     }
-    __shared__ double sh[kBlock];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *phi = 0.5 * sh[0];
+    s = block_sum(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// phi = 1/2 (sum of the nb block partials), one block, fixed order.
+__global__ __launch_bounds__(kBlock) void k_misfit_finalize(const double *partial, int32_t nb, double *phi) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) s += partial[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *phi = 0.5 * s;
 }
 
 // ---- batched step over many shots (serving) ------------------------------------
@@ -776,14 +801,25 @@ hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+int misfit_blocks(int32_t nrec, int64_t ncols) {
+    const int64_t n = (int64_t)nrec * ncols;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMisfitMaxBlocks));
+}
+
 hipError_t launch_misfit(int storage, const void *traces, const void *obs, void *res, int32_t nrec, int64_t cap,
-                         int64_t ncols, double *phi, hipStream_t s) {
+                         int64_t ncols, double *phi, double *partial, hipStream_t s) {
+    const int nb = misfit_blocks(nrec, ncols);
     if (storage == ST_F64)
-        hipLaunchKernelGGL(k_misfit<double>, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<const double *>(traces),
-                           reinterpret_cast<const double *>(obs), reinterpret_cast<double *>(res), nrec, cap, ncols, phi);
+        hipLaunchKernelGGL(k_misfit_partial<double>, dim3(nb), dim3(kBlock), 0, s,
+                           reinterpret_cast<const double *>(traces), reinterpret_cast<const double *>(obs),
+                           reinterpret_cast<double *>(res), nrec, cap, ncols, partial);
     else
-        hipLaunchKernelGGL(k_misfit<float>, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<const float *>(traces),
-                           reinterpret_cast<const float *>(obs), reinterpret_cast<float *>(res), nrec, cap, ncols, phi);
+        hipLaunchKernelGGL(k_misfit_partial<float>, dim3(nb), dim3(kBlock), 0, s,
+                           reinterpret_cast<const float *>(traces), reinterpret_cast<const float *>(obs),
+                           reinterpret_cast<float *>(res), nrec, cap, ncols, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_misfit_finalize, dim3(1), dim3(kBlock), 0, s, partial, nb, phi);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ struct Layout {
     int64_t pstride = 0, fpstride = 0;
     int64_t nblocks = 0;
     size_t pop[2] = {0, 0}, c2 = 0, rrow = 0, rxs = 0, rslot = 0;
-    size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0;
+    size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0, misfit = 0;
     size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, ring = 0, total = 0;
     size_t ckpt = 0, seg = 0, lam[2] = {0, 0};
 };
@@ -113,6 +113,7 @@ Layout make_layout(const lb_grid_desc *d) {
     L.nblocks = lbw::step_blocks(storage_kind(d->precision), d->nx, d->ny, false);
     L.partial = take((size_t)L.nblocks * 8);
     L.scratch = take(256);
+    L.misfit = take((size_t)lbw::kMisfitMaxBlocks * 8);
     if (d->patch_enable) {
         PatchGeom g = patch_geom(d);
         const int64_t nf = (int64_t)g.nxf * g.nyf;
@@ -924,8 +925,18 @@ int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res, double *d_
     if (!recording(h) || !(h->what & LB_FIELD_P)) return LB_E_STATE;
     if (nt < 0 || nt >= h->d.trace_capacity) return LB_E_RANGE;
     LB_TRY(h, lbw::launch_misfit(h->storage, h->traces, d_obs, d_res, h->nrec, h->d.trace_capacity, nt + 1, d_phi,
-                                 h->stream));
+                                 (double *)(h->ws + h->L.misfit), h->stream));
     return LB_OK;
+}
+
+int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_t nrec, int64_t cap, int64_t ncols,
+                    lb_dtype t, double *d_phi, void *d_workspace, size_t ws_bytes, void *stream) {
+    const int rc = lbw::check_trace_misfit(d_traces, d_obs, d_res, nrec, cap, ncols, t, d_phi);
+    if (rc) return rc;
+    if (!d_workspace || ((uintptr_t)d_workspace & 7u) || ws_bytes < (size_t)LB_TRACE_MISFIT_WORKSPACE_BYTES)
+        return LB_E_WORKSPACE;
+    return lbw::launch_misfit(t == LB_F64 ? lbw::ST_F64 : lbw::ST_F32, d_traces, d_obs, d_res, nrec, cap, ncols, d_phi,
+                              (double *)d_workspace, (hipStream_t)stream) == hipSuccess ? LB_OK : LB_E_HIP;
 }
 
 int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
@@ -1114,6 +1125,15 @@ Collision make_collision(const lb_grid_desc *d) {
         else momentum_exact_pair<float>(c.ratio, &c.kax, &c.kdg);
     }
     return c;
+}
+
+int check_trace_misfit(const void *traces, const void *obs, const void *res, int32_t nrec, int64_t cap,
+                       int64_t ncols, lb_dtype t, const double *phi) {
+    if (!traces || !obs || !res || !phi) return LB_E_INVALID;
+    if (t != LB_F32 && t != LB_F64 && t != LB_F16S) return LB_E_INVALID;
+    if (nrec < 1 || cap < 1 || ncols < 1 || ncols > cap) return LB_E_RANGE;
+    if (cap > INT64_MAX / nrec) return LB_E_RANGE;   // nrec x cap elements must be addressable
+    return LB_OK;
 }
 
 int validate_scheme(const lb_grid_desc *d) {

@@ -33,7 +33,9 @@ EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_blocked_steps", "lb_worksp
            "lb_status_string", "lb_device_copy",
            "lb_batch_workspace_bytes", "lb_batch_create", "lb_shot_workspace_bytes",
            "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times",
-           "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint")
+           "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint", "lb_trace_misfit")
+
+TRACE_MISFIT_WORKSPACE_BYTES = 16384   # LB_TRACE_MISFIT_WORKSPACE_BYTES
 
 
 class LBError(RuntimeError):
@@ -111,6 +113,7 @@ def lib():
         "lb_sync": (ctypes.c_int, [vp]),
         "lb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lb_device_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "lb_trace_misfit": (ctypes.c_int, [vp, vp, vp, i32, i64, i64, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]),
         "lb_batch_workspace_bytes": (ctypes.c_size_t, [i32]),
         "lb_batch_create": (ctypes.c_int, [PD, i32, vp, ctypes.c_size_t, vp, ctypes.c_int,
                                            ctypes.POINTER(vp)]),
@@ -380,6 +383,41 @@ def device_copy(dst, src, nbytes, stream=None):
     _check(lib().lb_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                                 ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(s.cuda_stream)),
            "lb_device_copy")
+
+
+def _misfit_args(traces, obs, ncols):
+    """Checked (traces, obs, res, phi, nrec, cap, ncols, dtype code) for the
+    trace-misfit entry points: traces and obs device tensors of one shape
+    [nrec][cap] and one dtype (float32 or float64)."""
+    import torch
+    if not (isinstance(traces, torch.Tensor) and isinstance(obs, torch.Tensor) and traces.is_cuda and obs.is_cuda):
+        raise TypeError("traces and obs must be CUDA tensors")
+    if traces.dim() != 2 or tuple(obs.shape) != tuple(traces.shape) or obs.dtype != traces.dtype:
+        raise ValueError("traces and obs must be [nrec][cap] tensors of one shape and dtype")
+    if traces.dtype not in (torch.float32, torch.float64):
+        raise TypeError("traces must be float32 or float64")
+    nrec, cap = (int(v) for v in traces.shape)
+    ncols = cap if ncols is None else int(ncols)
+    traces, obs = traces.contiguous(), obs.contiguous()
+    res = torch.zeros_like(traces)
+    phi = torch.zeros((), dtype=torch.float64, device=traces.device)
+    return traces, obs, res, phi, nrec, cap, ncols, (F64 if traces.dtype == torch.float64 else F32)
+
+
+def trace_misfit(traces, obs, ncols=None, stream=None):
+    """(phi, res) of lb_trace_misfit: res = traces - obs over the first
+    ncols columns (default all) and phi = 1/2 sum res^2 (FP64), with a
+    workspace tensor for the block partials."""
+    import torch
+    traces, obs, res, phi, nrec, cap, ncols, t = _misfit_args(traces, obs, ncols)
+    s = torch.cuda.current_stream(traces.device) if stream is None else stream
+    ws = torch.empty(TRACE_MISFIT_WORKSPACE_BYTES, dtype=torch.uint8, device=traces.device)
+    _check(lib().lb_trace_misfit(ctypes.c_void_p(traces.data_ptr()), ctypes.c_void_p(obs.data_ptr()),
+                                 ctypes.c_void_p(res.data_ptr()), nrec, cap, ncols, t,
+                                 ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(TRACE_MISFIT_WORKSPACE_BYTES), ctypes.c_void_p(s.cuda_stream)),
+           "lb_trace_misfit")
+    return phi, res
 
 
 def shot_desc(nx, ny, src, nsteps, nrec, sponge_width=0, sponge_sigma_max=0.0):

@@ -192,3 +192,27 @@ def test_trace_shaped_arrays_are_checked_before_any_launch(lw):
     finally:
         lw._LIB = saved
         g._h = None
+
+
+def test_trace_misfit_rejects_bad_arguments_before_any_launch(lw):
+    """lb_trace_misfit validates pointers, sizes, dtype and workspace on the
+    host; these calls fail before anything is enqueued (no GPU needed)."""
+    L = lw.lib()
+    p = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    nbytes = ctypes.c_size_t(lw.TRACE_MISFIT_WORKSPACE_BYTES)
+    call = lambda tr, ob, re, nrec, cap, ncols, t, phi, w, wb: L.lb_trace_misfit(
+        tr, ob, re, nrec, cap, ncols, t, phi, w, wb, None)
+    assert call(None, p, p, 3, 10, 10, 0, p, ws, nbytes) == -1
+    assert call(p, None, p, 3, 10, 10, 0, p, ws, nbytes) == -1
+    assert call(p, p, None, 3, 10, 10, 0, p, ws, nbytes) == -1
+    assert call(p, p, p, 3, 10, 10, 0, None, ws, nbytes) == -1
+    assert call(p, p, p, 3, 10, 10, 7, p, ws, nbytes) == -1          # no such dtype
+    assert call(p, p, p, 0, 10, 10, 0, p, ws, nbytes) == -2          # no receivers
+    assert call(p, p, p, 3, 10, 11, 0, p, ws, nbytes) == -2          # ncols > cap
+    assert call(p, p, p, 3, 10, 0, 0, p, ws, nbytes) == -2
+    assert call(p, p, p, 3, 0, 0, 0, p, ws, nbytes) == -2
+    assert call(p, p, p, 2, 2 ** 62, 10, 0, p, ws, nbytes) == -2     # nrec x cap beyond int64
+    assert call(p, p, p, 3, 10, 10, 0, p, None, nbytes) == -4
+    assert call(p, p, p, 3, 10, 10, 0, p, ws, ctypes.c_size_t(16383)) == -4
+    assert call(p, p, p, 3, 10, 10, 0, p, ctypes.c_void_p(0x200004), nbytes) == -4
