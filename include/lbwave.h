@@ -277,6 +277,26 @@ int lb_misfit(lb_grid *h, const void *d_obs, int64_t nt, void *d_res,
 int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_t nrec, int64_t cap,
                     int64_t ncols, lb_dtype t, double *d_phi, void *d_workspace, size_t ws_bytes, void *stream);
 
+/* lb_trace_misfit with no workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, same kernels and the
+ * same bits as lb_trace_misfit; it calls no hipMalloc, hipFree or allocating
+ * routine.  The block partials live in a static device array of 2048
+ * doubles (16 KiB) that every GPU the library runs on holds until the
+ * process ends; its address on the GPU of `stream` is looked up once per
+ * device.  That array bounds the number of blocks, not the input: any
+ * nrec x ncols is reduced by the grid-stride loop; sizes are rejected only
+ * as for lb_trace_misfit (LB_E_RANGE unless nrec >= 1, 1 <= ncols <= cap and
+ * nrec x cap fits int64).  Every call on one GPU shares that GPU's array:
+ * calls whose execution overlaps on one GPU (different streams, or several
+ * host threads) race and may return wrong sums; order them on one stream or
+ * synchronise between them.  The array keeps the last call's partials;
+ * each call writes every partial it reads, so nothing needs clearing.
+ * LB_E_HIP if the device or the array's address cannot be obtained or the
+ * launch fails. */
+int lb_trace_misfit_static(const void *d_traces, const void *d_obs, void *d_res, int32_t nrec, int64_t cap,
+                           int64_t ncols, lb_dtype t, double *d_phi, void *stream);
+
 /* Gradient of a trace misfit with respect to the per-node c^2 by the
  * discrete adjoint of the scheme (the paper's update differentiated exactly:
  * transpose of streaming and collision, source, sponge and receiver terms,

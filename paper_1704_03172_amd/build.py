@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbwave.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["lb_blocked_f32_q5.hip", "lb_blocked_f32_q9.hip", "lb_blocked_f64_q5.hip", "lb_blocked_f64_q9.hip",
-           "lb_blocked_f16_q5.hip", "lb_adjoint2.hip", "lb_kernels.hip", "lb_blocked.hip", "lb_runtime.cpp", "lb_batch.cpp"]
+           "lb_blocked_f16_q5.hip", "lb_adjoint2.hip", "lb_kernels.hip", "lb_blocked.hip", "lb_runtime.cpp", "lb_batch.cpp",
+           "lb_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LBWAVE_ARCH", "gfx950")
 

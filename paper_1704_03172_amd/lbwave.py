@@ -33,7 +33,8 @@ EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_blocked_steps", "lb_worksp
            "lb_status_string", "lb_device_copy",
            "lb_batch_workspace_bytes", "lb_batch_create", "lb_shot_workspace_bytes",
            "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times",
-           "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint", "lb_trace_misfit")
+           "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint", "lb_trace_misfit",
+           "lb_trace_misfit_static")
 
 TRACE_MISFIT_WORKSPACE_BYTES = 16384   # LB_TRACE_MISFIT_WORKSPACE_BYTES
 
@@ -114,6 +115,7 @@ def lib():
         "lb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lb_device_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "lb_trace_misfit": (ctypes.c_int, [vp, vp, vp, i32, i64, i64, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]),
+        "lb_trace_misfit_static": (ctypes.c_int, [vp, vp, vp, i32, i64, i64, ctypes.c_int, vp, vp]),
         "lb_batch_workspace_bytes": (ctypes.c_size_t, [i32]),
         "lb_batch_create": (ctypes.c_int, [PD, i32, vp, ctypes.c_size_t, vp, ctypes.c_int,
                                            ctypes.POINTER(vp)]),
@@ -417,6 +419,21 @@ def trace_misfit(traces, obs, ncols=None, stream=None):
                                  ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                  ctypes.c_size_t(TRACE_MISFIT_WORKSPACE_BYTES), ctypes.c_void_p(s.cuda_stream)),
            "lb_trace_misfit")
+    return phi, res
+
+
+def trace_misfit_static(traces, obs, ncols=None, stream=None):
+    """lb_trace_misfit_static: trace_misfit() with the block partials in the
+    library's static device array (no workspace).  Calls whose execution
+    overlaps on one GPU race; the output tensors are the caller's, as in
+    trace_misfit()."""
+    import torch
+    traces, obs, res, phi, nrec, cap, ncols, t = _misfit_args(traces, obs, ncols)
+    s = torch.cuda.current_stream(traces.device) if stream is None else stream
+    _check(lib().lb_trace_misfit_static(ctypes.c_void_p(traces.data_ptr()), ctypes.c_void_p(obs.data_ptr()),
+                                        ctypes.c_void_p(res.data_ptr()), nrec, cap, ncols, t,
+                                        ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+           "lb_trace_misfit_static")
     return phi, res
 
 
