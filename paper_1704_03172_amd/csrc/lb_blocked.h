@@ -449,6 +449,299 @@ __device__ __attribute__((always_inline)) inline void stepn_wave(const StepParam
     });
 }
 
+// ---- NS steps per launch over tall segments (marching) ---------------------------
+// The update of stepn_wave (the same stages in the same order, the same
+// per-node arithmetic, so the same bits) over segments of LY rows instead of
+// a few, which makes more steps per launch affordable: a segment reads
+// LY + 2 NS rows of h(n) and computes NS LY + NS (NS - 1) stage-rows for its
+// NS LY owned ones.  The walk is a loop whose body takes U consecutive walk
+// indices: row m of h(n) and of every intermediate state sits in ring slot
+// m mod U, a compile-time index in each copy of the body, so the rings stay
+// in registers.  Row m of h(n) is loaded PD walk indices before stage 1
+// first reads it; c^2 of row m, which the stages read at walk indices
+// m + 1 .. m + NS, goes through a small per-wave LDS ring (the register ring
+// then only spans the prefetch: U > PD + 2).  The strip carries
+// ceil(NS / V) halo lanes on each side.  Needs nx a multiple of V (vector
+// accesses) and ny >= LY + 2 NS (a row index wraps at most once);
+// march_ok() tells.
+template <typename S, int NS> struct MTb {
+    static constexpr int V = Tb<S>::V;
+    static constexpr int H = (NS + V - 1) / V;
+    static constexpr int OW = (64 - 2 * H) * V;
+};
+// Segment height, prefetch distance and ring length, measured at 4096^2 on
+// MI355X (us per step, D2Q5 FP32): eight steps per launch with LY = 24,
+// PD = 3 for BGK at tau = 1/2 (33.5; LY 18 / 30 / 36 / 42: 35.1 / 35.9 / 35.0
+// / 37.7, more tail waves or more halo; PD 2 with U = 5: 33.6 at 176
+// VGPRs, still two waves per SIMD) and six with PD = 2 for MRT, whose larger
+// collision makes the third wave per SIMD worth more than two steps
+// (40.2 at 152 VGPRs; eight steps 45.1, seven 44.0).
+template <typename S, int Q, int KIND, int NS> struct March {
+    static constexpr int LY = 24, PD = NS <= 6 ? 2 : 3, U = 6;
+    static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
+};
+
+template <typename S, int Q, int KIND, int NS>
+inline bool march_ok(int32_t nx, int32_t ny) {
+    return nx % Tb<S>::V == 0 && ny >= March<S, Q, KIND, NS>::LY + 2 * NS;
+}
+
+template <typename S, int Q, int KIND, int NS>
+inline int64_t march_waves(int32_t nx, int32_t ny) {
+    return (int64_t)((nx + MTb<S, NS>::OW - 1) / MTb<S, NS>::OW) *
+           ((ny + March<S, Q, KIND, NS>::LY - 1) / March<S, Q, KIND, NS>::LY);
+}
+
+// The launch parameters as read inside a rarely taken, wave-uniform branch
+// (receivers, source, sponge) of a kernel whose first (only) argument is the
+// StepParams: straight from the kernel-argument segment (scalar loads),
+// through a pointer whose value the compiler cannot follow, so that the
+// fields are loaded where the branch uses them rather than held in scalar
+// registers across the whole walk (the march kernel's many stages in flight
+// otherwise run out of them and spill).  Taking the address of the by-value
+// parameter instead would copy it to scratch memory.
+typedef const __attribute__((address_space(4))) StepParams *KernargParams;
+__device__ inline KernargParams rare_params() {
+    KernargParams q = (KernargParams)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+// One of eight arrays chosen at compile time.
+template <int I, typename A>
+__device__ inline A &pick8(A &a0, A &a1, A &a2, A &a3, A &a4, A &a5, A &a6, A &a7) {
+    if constexpr (I < 4) return pick4<I>(a0, a1, a2, a3);
+    else return pick4<I - 4>(a4, a5, a6, a7);
+}
+
+template <typename S, int Q, int KIND, int NS>
+__device__ __attribute__((always_inline)) inline void march_wave(const StepParams &p, int wave,
+                                                                 typename Tr<S>::T *c2ring) {
+    using T = typename Tr<S>::T;
+    using M = March<S, Q, KIND, NS>;
+    constexpr int V = MTb<S, NS>::V, H = MTb<S, NS>::H, OW = MTb<S, NS>::OW;
+    constexpr int LY = M::LY, PD = M::PD, U = M::U, CR = M::CR;
+    constexpr int K = LY + 2 * NS;
+    static_assert(NS >= 2 && NS <= 8 && H * V >= NS, "the strip halo must cover one column per step");
+    static_assert(U > PD + 2 && PD >= 1, "ring too short for the prefetch distance");
+    static_assert(LY % U == 0, "the loop over the walk has no tail");
+    static_assert(CR >= NS && (CR & (CR - 1)) == 0, "c^2 ring too short");
+    static_assert(LY + 1 <= 64, "the receiver row table of a segment is held one row per lane");
+    const int nx = p.nx, ny = p.ny;
+    const int nstrip = (nx + OW - 1) / OW;
+    const int nseg = (ny + LY - 1) / LY;
+    if ((int64_t)wave >= (int64_t)nstrip * nseg) return;
+    const int lane = threadIdx.x & 63;
+    const int sx = wave % nstrip, sy = wave / nstrip;
+    const int xl = sx * OW - H * V + lane * V;   // first column of this lane
+    const int y0 = sy * LY, y1 = min(y0 + LY, ny);
+    int xw[V];
+    bool own[V];
+    const bool own_lane = lane >= H && lane < 64 - H;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        xw[j] = wrapi(xl + j, nx);
+        own[j] = own_lane && xl + j < nx;
+    }
+    const int xv = xw[0];   // nx is a multiple of V: the lane's columns are xv .. xv + V - 1
+    const int L = p.sponge_width;
+    const bool strip_sponge = sx * OW - H * V < L || sx * OW - H * V + 64 * V - 1 >= nx - L;
+    int dxw[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) dxw[j] = min(xw[j], nx - 1 - xw[j]);
+    const S *src = reinterpret_cast<const S *>(p.src);
+    S *dst = reinterpret_cast<S *>(p.dst);
+    const T *c2 = reinterpret_cast<const T *>(p.c2);
+    const bool has_rec = p.rec.row_ptr != nullptr;
+    int rowv = 0;
+    if (has_rec && lane <= y1 - y0) rowv = p.rec.row_ptr[y0 + lane];
+    // row m of the segment (0 <= m < K) is unwrapped row y0 - NS + m
+    auto wrow = [&](int m) {
+        const int r = y0 - NS + m;
+        return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+    };
+    typedef typename LaneVec<V, T>::type ct;
+    // this lane's c^2 of row m in the LDS ring (slot m mod CR)
+    auto c2slot = [&](int m) { return reinterpret_cast<ct *>(c2ring + ((m & (CR - 1)) * 64 + lane) * V); };
+
+    // R: h(n) rows and their c^2; A1..A7: h(n+1) .. h(n+7) rows; row m in slot m % U
+    T R[U][Q][V], C[U][V], A1[U][Q][V], A2[U][Q][V], A3[U][Q][V], A4[U][Q][V], A5[U][Q][V], A6[U][Q][V],
+        A7[U][Q][V];
+    // rows shared with the neighbouring segments (the NS halo rows and NS edge
+    // rows on each side) keep the ordinary cache policy, the others stream
+    auto load = [&](auto slc, int m, auto selc) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slc)::value, SEL = decltype(selc)::value;
+        asm volatile("" : "+s"(m));
+        const int64_t ro = (int64_t)wrow(m) * nx;
+        if (m < 2 * NS || m >= K - 2 * NS) {
+            load_row2<true, SEL, true, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[SL]);
+            if constexpr (SEL == 0) load_c2row<true, true, T, V>(c2, ro, xv, xw, C[SL]);
+        } else {
+            load_row2<true, SEL, false, S, T, Q, V>(src, p.pstride, ro, xv, xw, R[SL]);
+            load_c2row<true, false, T, V>(c2, ro, xv, xw, C[SL]);
+        }
+    };
+    // rows 0 .. PD + 1 up front (of row 0 only the populations that stream
+    // into the segment)
+    static_for<0, PD + 2>([&](auto mc) __attribute__((always_inline)) {
+        constexpr int m = decltype(mc)::value;
+        load(std::integral_constant<int, m % U>{}, m, std::integral_constant<int, m == 0 ? 1 : 0>{});
+    });
+
+    // stage st (1..NS) at walk index k computes row m = k - st from rows
+    // m - 1, m, m + 1 of stage st - 1; KM is k mod U, known at compile time
+    auto stage = [&](auto stc, auto kmc, int k) __attribute__((always_inline)) {
+        constexpr int st = decltype(stc)::value, KM = decltype(kmc)::value;
+        constexpr int SM = (KM - st + 8 * U) % U, SU = (SM + U - 1) % U, SD = (SM + 1) % U;
+        // the row indices are recomputed in every stage (a few scalar
+        // operations): the compiler would otherwise keep each row's values
+        // for all the stages that reach it and run out of scalar registers
+        asm volatile("" : "+s"(k));
+        const int m = k - st;
+        const int gm = y0 - NS + m;           // unwrapped row
+        const bool owned_row = gm >= y0 && gm < y1;
+        if (st == NS && !owned_row) return;   // the last stage computes owned rows only
+        auto &A = pick8<st - 1>(R, A1, A2, A3, A4, A5, A6, A7);
+        const int wm = wrow(m);
+        // c^2 of row m: stage 1 takes it from the loaded row and puts it in
+        // the ring for the later stages
+        T cm[V];
+        if constexpr (st == 1) {
+            ct t;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                cm[j] = C[SM][j];
+                t[j] = cm[j];
+            }
+            *c2slot(m) = t;
+        } else {
+            const ct t = *c2slot(m);
+#pragma unroll
+            for (int j = 0; j < V; ++j) cm[j] = t[j];
+        }
+        T g[Q][V];
+        pull_row2<T, Q, V>(A[SU], A[SM], A[SD], g);
+        int rb = 0, re = 0;
+        if (has_rec && owned_row) {
+            rb = __builtin_amdgcn_readlane(rowv, m - NS);
+            re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
+        }
+        if (__builtin_expect(rb < re, 0)) {
+            const KernargParams q = rare_params();
+            Receivers rc;   // field by field: no copy constructor from this address space
+            rc.row_ptr = q->rec.row_ptr;
+            rc.xs = q->rec.xs;
+            rc.slot = q->rec.slot;
+            rc.traces = q->rec.traces;
+            rc.nslots = q->rec.nslots;
+            rc.what = q->rec.what;
+            rc.cap = q->rec.cap;
+            rc.col = q->rec.col + st - 1;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                T gj[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+                if (own[j]) record_node<T, Q>(rc, rb, re, xw[j], gj, cm[j]);
+            }
+        }
+        T pj[V][Q];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            T gj[Q], w[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gj[i] = g[i][j];
+            collide<T, Q, KIND>(gj, cm[j], p.coll, pj[j], w);
+        }
+        if (__builtin_expect(wm == p.src_y, 0)) {
+            const KernargParams q = rare_params();
+            const double snv = st == 1 ? q->s_n : st == 2 ? q->s_n2 : st == 3 ? q->s_n3 : st == 4 ? q->s_n4
+                                                                                        : q->s_more[(st - 5) & 3];
+            const int sxs = q->src_x;
+            Collision cl;   // the fields weights() reads
+            cl.kw = q->coll.kw;
+            cl.ratio = q->coll.ratio;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (xw[j] == sxs) {
+                    T w[Q];
+                    weights<T, Q>(cm[j], cl, w);
+                    add_source<T, Q>(w, snv, pj[j]);
+                }
+            }
+        }
+        const int dy = min(wm, ny - 1 - wm);
+        if (__builtin_expect(strip_sponge || dy < L, 0)) {
+            const double smax = rare_params()->sponge_smax;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int d = min(dxw[j], dy);
+                if (d < L) {
+                    asm volatile("");
+                    apply_sponge<T, Q>(d, L, smax, pj[j]);
+                }
+            }
+        }
+        if constexpr (st == NS) {   // owned row: the result of this launch
+            const int64_t ro = (int64_t)gm * nx;
+            if (own[0]) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    typedef typename LaneVec<V, S>::type vt;
+                    vt t;
+#pragma unroll
+                    for (int j = 0; j < V; ++j) t[j] = to_store<S>(pj[j][i]);
+                    __builtin_nontemporal_store(t, at_lane<vt>(dst + i * p.pstride + ro, xv));
+                }
+            }
+        } else {
+            // rounded to the storage format, as a stored h(n+st) would be
+            auto &B = pick8<st>(R, A1, A2, A3, A4, A5, A6, A7);
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) B[SM][i][j] = T(to_store<S>(pj[j][i]));
+        }
+    };
+    // the stages that run at walk index k (stage st from k = 2 st on)
+    auto stages = [&](auto kmc, int k, auto firstc) __attribute__((always_inline)) {
+        constexpr int FIRST = decltype(firstc)::value;   // -1: all stages run
+        static_for<1, NS + 1>([&](auto stc) __attribute__((always_inline)) {
+            constexpr int st = decltype(stc)::value;
+            if constexpr (FIRST < 0 || FIRST >= 2 * st) stage(stc, kmc, k);
+        });
+    };
+
+    // walk indices 2 .. 2 NS - 1: the stages start one after the other
+    static_for<2, 2 * NS>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        load(std::integral_constant<int, (k + PD) % U>{}, k + PD, std::integral_constant<int, 0>{});
+        stages(std::integral_constant<int, k % U>{}, k, std::integral_constant<int, k>{});
+    });
+    // walk indices 2 NS .. K - 1 (LY of them, U per pass): every stage runs
+    // and a row is loaded at every index (past the segment the last row
+    // again, an L2 hit), so that no ring slot is written conditionally and
+    // the values left in the slots are dead across the loop
+    for (int k0 = 2 * NS; k0 < K; k0 += U) {
+        static_for<0, U>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int J = decltype(jc)::value;
+            constexpr int KM = (2 * NS + J) % U;
+            const int k = k0 + J;
+            load(std::integral_constant<int, (KM + PD) % U>{}, min(k + PD, K - 1), std::integral_constant<int, 0>{});
+            stages(std::integral_constant<int, KM>{}, k, std::integral_constant<int, -1>{});
+        });
+    }
+}
+
+template <typename S, int Q, int KIND, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn_march(StepParams p) {
+    using T = typename Tr<S>::T;
+    constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
+    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    march_wave<S, Q, KIND, NS>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib]);
+}
+
 template <typename S, int Q, int KIND, bool VEC, int NS, bool RHO>
 __global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
     // wave-uniform (so that the row and loop arithmetic is scalar)
@@ -534,10 +827,49 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
     return (int64_t)((nx + Tb<S>::OW - 1) / Tb<S>::OW) * ((ny + ly - 1) / ly);
 }
 
+// Steps per launch of the marching kernel (march_wave) for a storage format,
+// lattice and collision kind (step_kind()), 0 where it is not instantiated.
+// Measured at 4096^2 (D2Q5 FP32 BGK at tau = 1/2): four steps per launch
+// marching 24-row segments ran at the speed of the 6-row kernel (45.0
+// against 44.4 us per step; both are held by the memory access pattern, not
+// by their arithmetic), so the marching kernel only takes the step counts
+// that the short segments cannot afford: eight for BGK (33.5 us per step),
+// six for MRT (see March).
+template <typename S, int Q, int KIND>
+constexpr int march_steps() { return std::is_same_v<S, float> && Q == 5 ? (KIND == 1 ? 6 : 8) : 0; }
+
+// The marching kernel's step count for a grid, 0 if it does not take it.
+template <typename S, int Q>
+int march_grid(int kind, int32_t nx, int32_t ny) {
+    auto one = [&](auto kc) {
+        constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
+        if constexpr (MN == 0) return 0;
+        else return march_ok<S, Q, KK, MN>(nx, ny) ? MN : 0;
+    };
+    return kind == 1 ? one(std::integral_constant<int, 1>())
+         : kind == 2 ? one(std::integral_constant<int, 2>()) : one(std::integral_constant<int, 0>());
+}
+
 // The single-grid NS-step launch for storage S and lattice Q.
 template <typename S, int Q>
 hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
     const int kind = step_kind(p.coll);
+    const int mn = march_grid<S, Q>(kind, p.nx, p.ny);
+    if (mn > 0 && ns == mn) {
+        if (p.rho_out != nullptr) return hipErrorInvalidValue;
+        auto launch = [&](auto kc) {
+            constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
+            if constexpr (MN > 0) {
+                const int64_t nw = march_waves<S, Q, KK, MN>(p.nx, p.ny);
+                const dim3 mgrid((unsigned)((nw + kT2Block / 64 - 1) / (kT2Block / 64)));
+                hipLaunchKernelGGL((k_stepn_march<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        };
+        return kind == 1 ? launch(std::integral_constant<int, 1>())
+             : kind == 2 ? launch(std::integral_constant<int, 2>()) : launch(std::integral_constant<int, 0>());
+    }
     const dim3 grid((unsigned)((waves_of<S, Q>(kind, ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
     // vector accesses need every lane's columns contiguous after the wrap
     const bool vec = p.nx % Tb<S>::V == 0;
@@ -592,12 +924,16 @@ hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hip
     hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s) {                    \
         return stepn_launch<SS, QQ>(p, ns, s);                                                      \
     }                                                                                               \
+    int march_steps_##NAME(int kind, int32_t nx, int32_t ny) {                                      \
+        return march_grid<SS, QQ>(kind, nx, ny);                                                    \
+    }                                                                                               \
     hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s) { \
         return stepn_batch_launch<SS, QQ>(bp, ns, nwaves, s);                                       \
     }
 
 #define LBW_BLOCKED_DECL(NAME)                                                                      \
     hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s);                     \
+    int march_steps_##NAME(int kind, int32_t nx, int32_t ny);                                       \
     hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s);
 LBW_BLOCKED_DECL(f32_q5)
 LBW_BLOCKED_DECL(f32_q9)

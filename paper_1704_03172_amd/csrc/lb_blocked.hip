@@ -4,6 +4,8 @@
 // batched executor's per-shot advance after a blocked launch.
 #include "lb_blocked.h"
 
+#include <algorithm>
+
 namespace lbw {
 namespace {
 
@@ -42,6 +44,24 @@ int stepn_max(int storage, int q, int kind) {
     });
 }
 
+int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny) {
+    if (nx < 1 || ny < 1) return 0;
+    if (storage == ST_F32) return q == 5 ? march_steps_f32_q5(kind, nx, ny) : march_steps_f32_q9(kind, nx, ny);
+    if (storage == ST_F64) return q == 5 ? march_steps_f64_q5(kind, nx, ny) : march_steps_f64_q9(kind, nx, ny);
+    if (storage == ST_F16 && q == 5) return march_steps_f16_q5(kind, nx, ny);
+    return 0;
+}
+
+int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny) {
+    return std::max(stepn_max(storage, q, kind == 1 ? 1 : 0), stepn_march(storage, q, kind, nx, ny));
+}
+
+int stepn_round(int storage, int q, int kind, int32_t nx, int32_t ny, int ns) {
+    const int mn = stepn_march(storage, q, kind, nx, ny);
+    if (mn > 0 && ns >= mn) return mn;
+    return std::max(1, std::min(ns, stepn_max(storage, q, kind == 1 ? 1 : 0)));
+}
+
 int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny) {
     return by_config(storage, q, [&](auto sv, auto qc) {
         return waves_of<decltype(sv), decltype(qc)::value>(kind, ns, nx, ny);
@@ -49,9 +69,10 @@ int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny
 }
 
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s) {
-    if (p.nx < 1 || p.ny < 1 || (p.q != 5 && p.q != 9) || ns < 2 || ns > stepn_max(storage, p.q, p.coll.kind) ||
-        p.nrun != ns)
-        return hipErrorInvalidValue;
+    if (p.nx < 1 || p.ny < 1 || (p.q != 5 && p.q != 9) || ns < 2 || p.nrun != ns) return hipErrorInvalidValue;
+    const int kind = step_kind(p.coll);
+    const bool march = ns == stepn_march(storage, p.q, kind, p.nx, p.ny) && p.rho_out == nullptr;
+    if (!march && ns > stepn_max(storage, p.q, p.coll.kind)) return hipErrorInvalidValue;
     if (storage == ST_F32) return p.q == 5 ? launch_stepn_f32_q5(p, ns, s) : launch_stepn_f32_q9(p, ns, s);
     if (storage == ST_F64) return p.q == 5 ? launch_stepn_f64_q5(p, ns, s) : launch_stepn_f64_q9(p, ns, s);
     if (storage == ST_F16 && p.q == 5) return launch_stepn_f16_q5(p, ns, s);

@@ -116,6 +116,7 @@ struct StepParams {
     double s_n2 = 0.0;                 // launch_stepn: source amplitudes of the second,
     double s_n3 = 0.0;                 // third and fourth steps
     double s_n4 = 0.0;
+    double s_more[4] = {0, 0, 0, 0};   // ... and of the fifth to eighth
     int32_t nrun = 1;                  // launch_stepn: steps this launch takes (= ns)
     int64_t rho_stride = 0;            // launch_stepn with rho_out: elements between the
                                        // rho fields of consecutive steps
@@ -225,12 +226,20 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull,
 // ns pull steps in one launch of the temporally blocked ns-step kernel
 // (p.nrun must equal ns): reads h(n) from p.src, writes h(n + ns) to p.dst
 // (a buffer other than p.src), records columns p.rec.col .. p.rec.col + ns - 1,
-// source amplitudes p.s_n .. p.s_n4; with p.rho_out, the pre-collision rho of
+// source amplitudes p.s_n .. p.s_n4, p.s_more; with p.rho_out, the pre-collision rho of
 // time n + s (s = 1..ns) goes to p.rho_out + (s - 1) * p.rho_stride.  No
 // reduction partials, snapshot or interface work.
-// 2 <= ns <= stepn_max(storage, p.q, p.coll.kind).
+// 2 <= ns <= stepn_max(storage, p.q, p.coll.kind), or ns = stepn_march(...)
+// without rho_out.
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
 int stepn_max(int storage, int q, int kind);   // steps per launch the blocked kernel offers (1: none)
+// Steps per launch of the marching kernel for an nx x ny grid (kind:
+// step_kind()), 0 where it does not apply; it takes exactly that count.
+int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny);
+// Most steps one launch takes on an nx x ny grid, and the largest step count
+// a launch can take that is at most ns (>= 1); kind is step_kind().
+int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny);
+int stepn_round(int storage, int q, int kind, int32_t nx, int32_t ny, int ns);
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
                                double *out, hipStream_t s);

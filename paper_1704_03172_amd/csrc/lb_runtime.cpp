@@ -66,7 +66,7 @@ int validate(const lb_grid_desc *d) {
     if (d->ckpt_every < 0 || d->ckpt_capacity < 0) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
-    if (d->steps_per_launch < 0 || d->steps_per_launch > 4) return LB_E_RANGE;
+    if (d->steps_per_launch < 0 || d->steps_per_launch > 8) return LB_E_RANGE;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -583,9 +583,12 @@ int lb_blocked_steps(const lb_grid_desc *d, int32_t *ns) {
     if (!d || !ns) return LB_E_INVALID;
     int rc = validate(d);
     if (rc) return rc;
-    int m = lbw::stepn_max(storage_kind(d->precision), d->lattice, d->collision);
+    const int sk = lbw::step_kind(lbw::make_collision(d));
+    int m = lbw::stepn_max_grid(storage_kind(d->precision), d->lattice, sk, d->nx, d->ny);
     if (d->patch_enable) m = 1;
-    if (d->steps_per_launch > 0) m = std::min(m, (int)d->steps_per_launch);
+    if (d->steps_per_launch > 0)
+        m = lbw::stepn_round(storage_kind(d->precision), d->lattice, sk, d->nx, d->ny,
+                             std::min(m, (int)d->steps_per_launch));
     *ns = m;
     return LB_OK;
 }
@@ -757,22 +760,25 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
     return LB_OK;
 }
 
-// Steps the next launch may take: the blocked kernel serves up to
-// stepn_max steps (capped by the descriptor's steps_per_launch), and a
-// launch from t to t+ns skips the states h(t+1) .. h(t+ns-1), so no
-// checkpoint column (whose launch pulls from h(col-1)) may fall in
-// t+2 .. t+ns.  left: steps still to take in this call; the last launch of
-// a call takes one step (the fields and the saved state of time t are read
-// from h(t-1)).
-// Steps per launch of the blocked kernel for this grid (1: none), capped by
-// the descriptor's steps_per_launch.
+// Steps per launch of the blocked kernels for this grid (1: none), capped by
+// the descriptor's steps_per_launch: up to stepn_max steps, and on grids
+// that the marching kernel takes also its (larger) step count.
 int blocked_max(const lb_grid *h) {
     if (h->patch) return 1;
-    int ns = lbw::stepn_max(h->storage, h->q, h->d.collision);
-    if (h->d.steps_per_launch > 0) ns = std::min(ns, h->d.steps_per_launch);
+    const int sk = lbw::step_kind(h->coll);
+    int ns = lbw::stepn_max_grid(h->storage, h->q, sk, h->d.nx, h->d.ny);
+    if (h->d.steps_per_launch > 0)
+        ns = lbw::stepn_round(h->storage, h->q, sk, h->d.nx, h->d.ny, std::min(ns, h->d.steps_per_launch));
     return ns;
 }
 
+// Steps the next launch may take: at most blocked_max, and a launch from t
+// to t+ns skips the states h(t+1) .. h(t+ns-1), so no checkpoint column
+// (whose launch pulls from h(col-1)) may fall in t+2 .. t+ns.  left: steps
+// still to take in this call; the last launch of a call takes one step (the
+// fields and the saved state of time t are read from h(t-1)).  The count is
+// rounded down to one a kernel takes (1 .. stepn_max, or the marching
+// kernel's).
 int blocked_steps(const lb_grid *h, int64_t left) {
     if (h->patch || h->sum_rho) return 1;
     int ns = blocked_max(h);
@@ -783,7 +789,8 @@ int blocked_steps(const lb_grid *h, int64_t left) {
                 ns = k - 1;
                 break;
             }
-    return std::max(ns, 1);
+    if (ns < 2) return 1;
+    return lbw::stepn_round(h->storage, h->q, lbw::step_kind(h->coll), h->d.nx, h->d.ny, ns);
 }
 
 // Steps t -> t+ns in one launch of the blocked kernel (columns t+1 .. t+ns).
@@ -801,6 +808,7 @@ int blocked_launch(lb_grid *h, int ns) {
     p.s_n2 = source_at(h, col + 1);
     p.s_n3 = source_at(h, col + 2);
     p.s_n4 = source_at(h, col + 3);
+    for (int k = 0; k < 4; ++k) p.s_more[k] = source_at(h, col + 4 + k);
     p.nrun = ns;
     if (recording(h)) attach_receivers(h, g, p, col);
     LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));
@@ -997,7 +1005,11 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
             p.dst = g.prevp();
             p.s_n = source_at(h, m);
             p.rho_out = (char *)h->seg + (size_t)(m - a) * n_nodes * tsz;
-            const int ns = pull ? (int)std::min<int64_t>(blocked_max(h), b - m + 1) : 1;
+            // (the rho-writing kernel takes up to stepn_max steps)
+            const int ns = pull ? (int)std::min<int64_t>(
+                                      std::min(blocked_max(h), lbw::stepn_max(h->storage, h->q, h->d.collision)),
+                                      b - m + 1)
+                                : 1;
             if (ns > 1) {
                 p.s_n2 = source_at(h, m + 1);
                 p.s_n3 = source_at(h, m + 2);

@@ -79,7 +79,9 @@ def test_desc_layout_matches_c(lw):
     (dict(steps_per_launch=1), 0),
     (dict(steps_per_launch=3), 0),
     (dict(steps_per_launch=4), 0),
-    (dict(steps_per_launch=5), -2),
+    (dict(steps_per_launch=5), 0),
+    (dict(steps_per_launch=8), 0),
+    (dict(steps_per_launch=9), -2),
     (dict(steps_per_launch=-1), -2),
 ])
 def test_validate(lw, kw, code):
@@ -90,21 +92,28 @@ def test_validate(lw, kw, code):
     assert (nb > 0) == (code == 0)
 
 
-@pytest.mark.parametrize("q,coll,prec,ns", [
-    (5, "bgk", "f32", 4), (5, "mrt", "f32", 4), (5, "bgk", "f64", 4), (5, "mrt", "f16s", 3),
-    (9, "bgk", "f32", 3), (9, "mrt", "f32", 3), (9, "mrt", "f64", 4), (9, "bgk", "f16s", 1)])
-def test_blocked_steps(lw, q, coll, prec, ns):
-    """Steps per launch of lb_step_n for each configuration, the cap of
-    steps_per_launch, one step with a patch, and the validation errors."""
+@pytest.mark.parametrize("q,coll,prec,ns,nsm", [
+    (5, "bgk", "f32", 4, 8), (5, "mrt", "f32", 4, 6), (5, "bgk", "f64", 4, 4), (5, "mrt", "f16s", 3, 3),
+    (9, "bgk", "f32", 3, 3), (9, "mrt", "f32", 3, 3), (9, "mrt", "f64", 4, 4), (9, "bgk", "f16s", 1, 1)])
+def test_blocked_steps(lw, q, coll, prec, ns, nsm):
+    """Steps per launch of lb_step_n for each configuration: ns with the
+    short-segment kernel, nsm where the marching kernel takes the grid
+    (D2Q5 FP32, ny >= 24 + 2 nsm: eight steps for BGK, six for MRT); the
+    cap of steps_per_launch (rounded
+    down to a count a kernel takes), one step with a patch, and the
+    validation errors."""
     kw = dict(nx=64, ny=64, lattice=q, collision=coll, precision=prec, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])
-    assert lw.blocked_steps(**kw) == ns
-    for cap in (1, 2, 3, 4):
-        assert lw.blocked_steps(steps_per_launch=cap, **kw) == min(cap, ns)
+    assert lw.blocked_steps(**kw) == nsm
+    assert lw.blocked_steps(**dict(kw, ny=23 + 2 * nsm)) == ns   # too short for the marching kernel
+    assert lw.blocked_steps(**dict(kw, nx=63)) == ns        # odd width: no vector accesses
+    for cap in range(1, 9):
+        want = nsm if cap >= nsm else min(cap, ns)
+        assert lw.blocked_steps(steps_per_launch=cap, **kw) == want
     kw.update(nx=256, ny=256)
     if lw.validate(patch=(96, 96, 64, 64), **kw) == 0:   # patches take D2Q5
         assert lw.blocked_steps(patch=(96, 96, 64, 64), **kw) == 1
     with pytest.raises(lw.LBError):
-        lw.blocked_steps(steps_per_launch=5, **kw)
+        lw.blocked_steps(steps_per_launch=9, **kw)
     assert lw.lib().lb_blocked_steps(None, None) == -1
 
 
