@@ -5,19 +5,20 @@ anomalies, 64-node sponge, Ricker source at >= 20 nodes per wavelength and
 256 surface receivers; D2Q5, BGK tau = 1/2, FP32 populations.  One "step" is
 one time step of the whole grid (pull-stream, moments, per-node weights,
 linear equilibrium, collision, source, sponge, receiver sampling at every
-time).  lb_step_n runs several steps per fused launch (four for this
-configuration, as lb_blocked_steps reports; the last launch of a call takes
-one), so the dominant kernel is the temporally blocked kernel: it reads h(n)
-and writes h(n+4), 44 algorithmic bytes per node per launch (24 read, 20
-written), i.e. 11 bytes per lattice update.  Inputs are resident in HBM
-before the timed region.
+time).  lb_step_n runs several steps per fused launch (eight for this
+configuration, as lb_blocked_steps reports, through the marching kernel;
+the last launch of a call takes one), so the dominant kernel is the marching
+kernel: it reads h(n) and writes h(n+8), 44 algorithmic bytes per node per
+launch (24 read, 20 written), i.e. 5.5 bytes per lattice update.  Inputs
+are resident in HBM before the timed region.
 
-Prints ONE JSON line: MLUPS (value), roofline of the blocked kernel (its
+Prints ONE JSON line: MLUPS (value), roofline of the dominant kernel (its
 launch duration measured with HIP events as the difference of two runs that
-differ only in the number of blocked launches, against the 8 TB/s HBM peak),
-a measured device-copy bandwidth, comparison variants (MRT, D2Q9, FP64, FP16
-storage, refinement, the 128^2 pulse), the adjoint and serving measurements
-and the CPU oracle timed on a bounded sample.
+differ only in the number of multi-step launches, against the 8 TB/s HBM
+peak), a measured device-copy bandwidth, comparison variants (MRT, D2Q9,
+FP64, FP16 storage with its error against an FP64 run, refinement, the 128^2
+pulse), the adjoint and serving measurements and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import json
@@ -42,20 +43,28 @@ def bytes_per_lup(q, precision):
     return 2 * q * s + c
 
 
-def max_steps_per_launch(lbwave, q, collision, precision):
-    """Steps per launch the blocked kernel takes for a configuration (the
-    library's lb_blocked_steps)."""
-    return lbwave.blocked_steps(nx=64, ny=64, lattice=q, collision=collision, precision=precision)
+def steps_rounding(lbwave, n, q, collision, precision):
+    """(most steps per launch, rounding) for an n x n grid of a
+    configuration, from the library's lb_blocked_steps: rounding[c] is the
+    step count a launch takes when at most c are allowed (a launch takes
+    1 .. 4 steps, or the marching kernel's count)."""
+    kw = dict(nx=n, ny=n, lattice=q, collision=collision, precision=precision,
+              s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])
+    ns_max = lbwave.blocked_steps(**kw)
+    rounding = {c: lbwave.blocked_steps(steps_per_launch=c, **kw) for c in range(1, 9)}
+    return ns_max, rounding
 
 
-def launch_plan(nsteps, ns_max):
+def launch_plan(nsteps, ns_max, rounding):
     """{steps per launch: launches} of one lb_step_n(nsteps) call on a grid
-    without patch, sum-of-rho recording or checkpoints: each launch takes
-    min(ns_max, steps left - 1) steps, the last one a single step."""
+    without patch, sum-of-rho recording or checkpoints, as the library takes
+    it: each launch takes min(ns_max, steps left - 1) steps rounded down to
+    a count a kernel takes, the last one a single step."""
     plan = {}
     k = 0
     while k < nsteps:
-        ns = max(1, min(ns_max, nsteps - k - 1))
+        c = max(1, min(ns_max, nsteps - k - 1))
+        ns = rounding[c]
         plan[ns] = plan.get(ns, 0) + 1
         k += ns
     return plan
@@ -177,7 +186,9 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
     finite = bool(torch.isfinite(grad).all().item())
     g.close()
     N = n * n
-    ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32")
+    # the recompute writes each step's rho, through the short-segment kernel
+    # (steps_per_launch=4 gives its count)
+    ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32", steps_per_launch=4)
     return {"workload": "%d shots, %dx%d, %d steps, checkpoints every %d, FP32 state, FP64 gradient"
                         % (nshots, n, n, nsteps, K),
             "seconds_total": round(wall, 3), "ms_per_shot": round(wall / nshots * 1e3, 2),
@@ -207,14 +218,27 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
+def kernel_label(nsl):
+    """Name of the kernel that takes the nsl-step launches of the headline
+    configuration (the marching kernel takes six or eight steps)."""
+    if nsl in (6, 8):
+        return "k_stepn_march<float,5,BGK tau=1/2,%d>" % nsl
+    return "k_stepn<float,5,BGK tau=1/2,%d>" % nsl
+
+
+def counters_profile(nsl):
+    """The committed rocprofv3 HBM-counter summary of the headline kernel."""
+    stem = "k_stepn_march%d" % nsl if nsl in (6, 8) else "k_stepn%d" % nsl
+    return os.path.join(ROOT, "profiles", stem + "_d2q5_bgk_f32_layered4096_hbm_counters.md")
+
+
 def measured_traffic(nsl):
-    """HBM bytes per blocked launch of nsl steps from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
-    factors), or None when the kernel sources changed after the counters
-    were taken."""
-    prof = os.path.join(ROOT, "profiles", "k_stepn%d_d2q5_bgk_f32_layered4096_hbm_counters.md" % nsl)
+    """HBM bytes per multi-step launch of nsl steps from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE scaled by the
+    copy-kernel factors), or None when the kernel sources changed after the
+    counters were taken."""
     try:
-        text = open(prof).read()
+        text = open(counters_profile(nsl)).read()
         sha = kernel_source_sha256()
     except OSError:
         return None
@@ -222,6 +246,29 @@ def measured_traffic(nsl):
     if fields.get("kernel_source_sha256", "").strip() != sha:
         return None
     return int(fields["traffic_bytes_per_launch"])
+
+
+def fp16_error(lbwave, inputs, n=512, nsteps=1000):
+    """Error of FP16 population storage on a bounded cut of the layered
+    workload (n^2, nsteps steps): relative L2 of the pressure traces and of
+    the final rho field against an FP64 run of the same cut (the FP64 path
+    is the one the parity tests hold to 1e-12 of the FP64 oracle)."""
+    wl = inputs.layered_workload(n=n, nsteps=nsteps + 1)
+    out = {}
+    for prec in ("f64", "f16s"):
+        g = make_layered(lbwave, wl, 5, "bgk", prec, nsteps + 1)
+        g.step(nsteps)
+        out[prec] = (g.traces[0][:, :nsteps + 1].double().cpu().numpy(), g.field("rho").double().cpu().numpy())
+        g.close()
+        del g
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    return {"trace_relL2": rel(out["f16s"][0], out["f64"][0]),
+            "rho_relL2": rel(out["f16s"][1], out["f64"][1]),
+            "cut": "%dx%d layered workload, %d steps, D2Q5 BGK tau=1/2" % (n, n, nsteps),
+            "reference": "FP64 GPU run of the same cut"}
 
 
 def cpu_baseline(wl, target_s=10.0):
@@ -327,7 +374,7 @@ def main():
     N = wl["nx"] * wl["ny"]
     cap = steps + warmup + 1
 
-    nsl = max_steps_per_launch(lbwave, 5, "bgk", "f32")
+    nsl, rounding = steps_rounding(lbwave, args.n, 5, "bgk", "f32")
     grid = make_layered(lbwave, wl, 5, "bgk", "f32", cap + 2 * steps + nsl * 501 + 10)
     log("timing D2Q5 BGK FP32: %d warmup + %d steps" % (warmup, steps))
     t = time_steps(torch, grid, steps, warmup)
@@ -335,7 +382,7 @@ def main():
     # gives `value`) with the median of the three
     windows = [t] + [time_steps(torch, grid, steps, 0) for _ in range(2)]
     mlups = N * steps / t / 1e6
-    plan = launch_plan(steps, nsl)
+    plan = launch_plan(steps, nsl, rounding)
     # the blocked kernel's launch duration: two calls that differ only in
     # their number of nsl-step launches (400 vs 100, one one-step launch each)
     ta = time_steps(torch, grid, nsl * 400 + 1, 0)
@@ -360,18 +407,23 @@ def main():
             g = make_layered(lbwave, wl, q, coll, prec, vsteps + 11)
             tv = time_steps(torch, g, vsteps, 10)
             b = bytes_per_lup(q, prec)
-            vplan = launch_plan(vsteps, max_steps_per_launch(lbwave, q, coll, prec))
+            vplan = launch_plan(vsteps, *steps_rounding(lbwave, args.n, q, coll, prec))
             nb = b * N * sum(vplan.values())      # algorithmic bytes of the launches
-            variants["D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())] = {
+            key = "D2Q%d_%s_%s" % (q, coll.upper(), prec.upper())
+            variants[key] = {
                 "MLUPS": round(N * vsteps / tv / 1e6, 1),
                 "GBs": round(nb / tv / 1e9, 1),
                 "frac_hbm": round(nb / tv / 1e9 / HBM_PEAK_GBS, 4),
                 "bytes_per_node_per_launch": b, "steps": vsteps,
                 "launches_by_steps": {str(k): v for k, v in sorted(vplan.items())}}
-            log("variant %s %.0f MLUPS" % (list(variants)[-1], N * vsteps / tv / 1e6))
+            log("variant %s %.0f MLUPS" % (key, N * vsteps / tv / 1e6))
             g.close()
             del g
             torch.cuda.empty_cache()
+            if prec == "f16s":
+                variants[key]["error_vs_fp64"] = fp16_error(lbwave, inputs)
+                log("FP16 storage error %s" % variants[key]["error_vs_fp64"])
+                torch.cuda.empty_cache()
         variants.update(refined_variant(torch, lbwave, inputs))
         variants.update(pulse_variant(torch, lbwave, inputs))
 
@@ -413,13 +465,20 @@ def main():
                                "(lattice units), 64-node sponge, Ricker source, 256 receivers",
                    "nx": wl["nx"], "ny": wl["ny"], "lattice": "D2Q5", "collision": "BGK tau=1/2",
                    "steps_timed": steps, "receivers": int(len(wl["receivers"]))},
+        # bound: of the kernel's two floors, the compulsory HBM traffic (44 B
+        # per node per launch at 8 TB/s) lies above the ALU one (16 FP32
+        # operations per update, unpacked, at 256 CUs x 64 lanes x 2.4 GHz);
+        # its counters show neither saturated (latency-bound at two waves per
+        # SIMD)
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-                     "kernel": "k_stepn<float,5,BGK tau=1/2,%d> (%d steps per launch)" % (nsl, nsl),
+                     "kernel": "%s (%d steps per launch)" % (kernel_label(nsl), nsl),
                      "algorithmic_bytes_per_launch": bpl * N, "lattice_updates_per_launch": nsl * N,
-                     "avg_kernel_us": round(kern_s * 1e6, 3)},
+                     "avg_kernel_us": round(kern_s * 1e6, 3),
+                     "hbm_floor_us": round(bpl * N / HBM_PEAK_GBS / 1e3, 3),
+                     "alu_floor_us": round(16.0 * nsl * N / (256 * 64 * 2.4e9) * 1e6, 3)},
         # the bytes a one-step-per-launch path would move per step (44 per
         # node), over the measured time per step: temporal blocking lifts this
         # above the HBM peak
