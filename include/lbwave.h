@@ -229,6 +229,27 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum);
  * work, then the two fine sub-steps). */
 int lb_step_n(lb_grid *h, int64_t n);
 
+/* Graph replay of lb_step_n, for grids whose steps are too short to hide
+ * the cost of issuing their launches one by one (the time loop of the
+ * evolution equation, Sec. II B).  steps = 0 turns it off (the default);
+ * 2 <= steps <= LB_GRAPH_MAX_STEPS makes lb_step_n run each whole chunk of
+ * `steps` steps of a call as one replay of a captured HIP graph, and the
+ * rest of the call as before.  A chunk's launches take the most steps the
+ * multi-step kernel offers (four; three for D2Q9 FP32 and FP16 storage) or
+ * one step, the last launch one step; one-step launches only where
+ * steps_per_launch caps the count lower, the width is not a multiple of the
+ * kernel's vector width or the sum of rho is recorded.  One small launch
+ * before each replay hands the graph the chunk's first time and source
+ * amplitudes, so one captured graph serves every chunk.  The graph is
+ * captured on the first chunk (and again after lb_set_source, lb_record,
+ * lb_record_sum_rho, lb_adjoint or lb_set_graph on the handle) and held
+ * until lb_destroy_grid.  The results are the same bits as without replay.
+ * Returns LB_E_RANGE for other step counts and LB_E_UNSUPPORTED for a grid
+ * with a patch or one bound to the null stream (which cannot be captured);
+ * while checkpoints are live, lb_step_n launches as without replay. */
+#define LB_GRAPH_MAX_STEPS 256
+int lb_set_graph(lb_grid *h, int32_t steps);
+
 /* Current time n of the handle (pre-collision state at time n). */
 int lb_get_time(const lb_grid *h, int64_t *n);
 

@@ -749,6 +749,15 @@ __global__ __launch_bounds__(kT2Block) void k_stepn(StepParams p) {
     stepn_wave<S, Q, KIND, VEC, NS, true, RHO>(p, xcd_block() * (kT2Block / 64) + wib, NS);
 }
 
+// An NS-step launch of a replayed graph (lane columns contiguous, NS the
+// most steps the kernel offers).
+template <typename S, int Q, int KIND, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn_graph(StepParams p) {
+    const StepParams q = graph_params(p);
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    stepn_wave<S, Q, KIND, true, NS, true, false>(q, xcd_block() * (kT2Block / 64) + wib, NS);
+}
+
 // Up to NS steps of every active shot in one launch (a shot takes
 // min(NS, bp.max_run, steps left)): wave w belongs to the active shot a with
 // wprefix[a] <= w < wprefix[a+1] (waves of nstrip x nseg per shot).
@@ -856,7 +865,8 @@ hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
     const int kind = step_kind(p.coll);
     const int mn = march_grid<S, Q>(kind, p.nx, p.ny);
     if (mn > 0 && ns == mn) {
-        if (p.rho_out != nullptr) return hipErrorInvalidValue;
+        // the marching kernel takes its times from the params only
+        if (p.rho_out != nullptr || p.gtab != nullptr) return hipErrorInvalidValue;
         auto launch = [&](auto kc) {
             constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
             if constexpr (MN > 0) {
@@ -873,6 +883,20 @@ hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
     const dim3 grid((unsigned)((waves_of<S, Q>(kind, ns, p.nx, p.ny) + kT2Block / 64 - 1) / (kT2Block / 64)));
     // vector accesses need every lane's columns contiguous after the wrap
     const bool vec = p.nx % Tb<S>::V == 0;
+    if (p.gtab) {   // a launch of a captured chunk: its own entry kernel, for the most steps only
+        if (!vec || p.rho_out) return hipErrorInvalidValue;
+        auto launch = [&](auto kc) {
+            constexpr int KK = decltype(kc)::value, NS = tn_max<S, Q, KK>();
+            if constexpr (NS >= 2) {
+                if (ns != NS) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_stepn_graph<S, Q, KK, NS>), grid, dim3(kT2Block), 0, s, p);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        };
+        return kind == 1 ? launch(std::integral_constant<int, 1>())
+             : kind == 2 ? launch(std::integral_constant<int, 2>()) : launch(std::integral_constant<int, 0>());
+    }
     return by_steps<S, Q>(ns, [&](auto nc) {
         constexpr int NS = decltype(nc)::value;
         auto launch = [&](auto kc) {

@@ -44,6 +44,15 @@ int stepn_max(int storage, int q, int kind) {
     });
 }
 
+int stepn_graph_steps(int storage, int q, int kind, int32_t nx) {
+    return by_config(storage, q, [&](auto sv, auto qc) {
+        using S = decltype(sv);
+        constexpr int Q = decltype(qc)::value;
+        const int m = kind == 1 ? tn_max<S, Q, 1>() : tn_max<S, Q, 0>();
+        return m >= 2 && nx % Tb<S>::V == 0 ? m : 1;
+    });
+}
+
 int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny) {
     if (nx < 1 || ny < 1) return 0;
     if (storage == ST_F32) return q == 5 ? march_steps_f32_q5(kind, nx, ny) : march_steps_f32_q9(kind, nx, ny);

@@ -84,6 +84,17 @@ struct InterfaceParams {
 };
 
 // One launch of the fused step (or of the collide-only variant).
+// Times of the launches of a captured graph that lb_step_n replays: the
+// launches carry times relative to the first time t0 of the replayed chunk,
+// and t0 and the chunk's source amplitudes s[k] = S(t0 + 1 + k) sit here, in
+// device memory that the host fills (one small launch) before each replay.
+constexpr int kGraphMaxSteps = 256;
+struct GraphTab {
+    int64_t t0 = 0;
+    int64_t pad = 0;
+    double s[kGraphMaxSteps + 8] = {};   // (zeros past the chunk: a launch reads four)
+};
+
 struct StepParams {
     const void *src = nullptr;         // populations read
     void *dst = nullptr;               // populations written
@@ -120,6 +131,8 @@ struct StepParams {
     int32_t nrun = 1;                  // launch_stepn: steps this launch takes (= ns)
     int64_t rho_stride = 0;            // launch_stepn with rho_out: elements between the
                                        // rho fields of consecutive steps
+    const GraphTab *gtab = nullptr;    // graph replay: rec.col is relative to gtab->t0 and
+    int32_t goff = 0;                  // the source amplitudes are gtab->s[goff ..]
 };
 
 // One backward step of the discrete adjoint (misfit gradient w.r.t. c^2):
@@ -230,9 +243,13 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull,
 // time n + s (s = 1..ns) goes to p.rho_out + (s - 1) * p.rho_stride.  No
 // reduction partials, snapshot or interface work.
 // 2 <= ns <= stepn_max(storage, p.q, p.coll.kind), or ns = stepn_march(...)
-// without rho_out.
+// without rho_out or gtab; with gtab ns = stepn_graph_steps(...) only.
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
 int stepn_max(int storage, int q, int kind);   // steps per launch the blocked kernel offers (1: none)
+// Steps of the multi-step launches of a captured chunk (p.gtab set): the
+// most the kernel offers, on grids whose width the vector loads take; 1:
+// the chunk takes one-step launches only.
+int stepn_graph_steps(int storage, int q, int kind, int32_t nx);
 // Steps per launch of the marching kernel for an nx x ny grid (kind:
 // step_kind()), 0 where it does not apply; it takes exactly that count.
 int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny);
@@ -241,8 +258,12 @@ int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny);
 int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny);
 int stepn_round(int storage, int q, int kind, int32_t nx, int32_t ny, int ns);
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
+// Sum of the nblocks partials to out[0], or (gtab set: a replayed graph) to
+// out[gtab->t0].
 hipError_t launch_sum_finalize(const double *partial, int64_t nblocks,
-                               double *out, hipStream_t s);
+                               double *out, const GraphTab *gtab, hipStream_t s);
+// *dst = val on the device, in stream order (before a graph replay).
+hipError_t launch_graph_prime(GraphTab *dst, const GraphTab &val, hipStream_t s);
 hipError_t launch_equilibrium(int storage, int32_t q, void *pop,
                               int64_t pstride, const void *c2,
                               const void *rho, const void *jx, const void *jy,

@@ -346,7 +346,7 @@ __device__ inline double update_tile(const StepParams &p, int x0, int y) {
 }
 
 template <typename S, int Q, int KIND, bool PULL>
-__global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
+__device__ __attribute__((always_inline)) inline void step_body(const StepParams &p) {
     constexpr int V = PULL ? Tr<S>::V : 1;
     if constexpr (Q == 5 && !kIsF64<S>) {
         // leading block rows of a coarse launch: the fine outer-ring states
@@ -374,6 +374,18 @@ __global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
             p.partial[(int64_t)y * gridDim.x + blockIdx.x] = s;
         }
     }
+}
+
+template <typename S, int Q, int KIND, bool PULL>
+__global__ __launch_bounds__(kStepBlock) void k_step(StepParams p) {
+    step_body<S, Q, KIND, PULL>(p);
+}
+
+// A one-step launch of a replayed graph (pull-stream, no interface work).
+template <typename S, int Q, int KIND>
+__global__ __launch_bounds__(kStepBlock) void k_step_graph(StepParams p) {
+    const StepParams q = graph_params(p);
+    step_body<S, Q, KIND, true>(q);
 }
 
 // ---- discrete adjoint (gradient of the trace misfit w.r.t. c^2) -----------------
@@ -572,7 +584,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_advance(ShotState *state, cons
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_finalize(const double *partial, int64_t n, double *out) {
+__global__ __launch_bounds__(kBlock) void k_sum_finalize(const double *partial, int64_t n, double *out,
+                                                          const GraphTab *gtab) {
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += kBlock) s += partial[i];
     __shared__ double sh[kBlock];
@@ -582,7 +595,14 @@ __global__ __launch_bounds__(kBlock) void k_sum_finalize(const double *partial, 
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) out[gtab ? gtab->t0 : 0] = sh[0];
+}
+
+// The chunk table of a graph replay, copied from the kernel arguments.
+__global__ __launch_bounds__(kBlock) void k_graph_prime(GraphTab *dst, GraphTab val) {
+    double *d = reinterpret_cast<double *>(dst);
+    const double *v = reinterpret_cast<const double *>(&val);
+    for (int i = threadIdx.x; i < (int)(sizeof(GraphTab) / 8); i += kBlock) d[i] = v[i];
 }
 
 // ---- set-up kernels --------------------------------------------------------
@@ -724,6 +744,17 @@ hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
             else hipLaunchKernelGGL((k_prolong_pair<S, 0>), pg, dim3(kBlock), 0, s, p0.iface);
         }
     }
+    if (p.gtab) {   // a launch of a captured chunk: its own entry kernel
+        if (!pull || p.prolong_on || p.restrict_on || p.snap || p.ring_buf) return hipErrorInvalidValue;
+#define LBW_GRAPH(QQ, KK) hipLaunchKernelGGL((k_step_graph<S, QQ, KK>), grid, dim3(kStepBlock), 0, s, p)
+        if (p.q == 5) {
+            if (kind == 0) LBW_GRAPH(5, 0); else if (kind == 2) LBW_GRAPH(5, 2); else LBW_GRAPH(5, 1);
+        } else {
+            if (kind == 0) LBW_GRAPH(9, 0); else if (kind == 2) LBW_GRAPH(9, 2); else LBW_GRAPH(9, 1);
+        }
+#undef LBW_GRAPH
+        return hipGetLastError();
+    }
 #define LBW_LAUNCH(QQ, KK, PP) \
     hipLaunchKernelGGL((k_step<S, QQ, KK, PP>), grid, dim3(kStepBlock), 0, s, p)
     if (p.q == 5) {
@@ -823,8 +854,15 @@ hipError_t launch_misfit(int storage, const void *traces, const void *obs, void 
     return hipGetLastError();
 }
 
-hipError_t launch_sum_finalize(const double *partial, int64_t nblocks, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+hipError_t launch_sum_finalize(const double *partial, int64_t nblocks, double *out, const GraphTab *gtab,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out, gtab);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_prime(GraphTab *dst, const GraphTab &val, hipStream_t s) {
+    static_assert(sizeof(GraphTab) % 8 == 0 && sizeof(GraphTab) <= 4096, "the table travels as a kernel argument");
+    hipLaunchKernelGGL(k_graph_prime, dim3(1), dim3(kBlock), 0, s, dst, val);
     return hipGetLastError();
 }
 

@@ -285,6 +285,24 @@ __device__ inline void write_fields(const Receivers &rc, int slot, T rho, T jx, 
     if (rc.what & 8u) { tr[f * plane + base] = jy; ++f; }
 }
 
+// The params of a launch replayed from a captured graph with its times made
+// absolute: the launch holds them relative to the chunk's first time, which
+// with the chunk's source amplitudes sits in the chunk table (GraphTab).
+// The graph entry kernels run the ordinary bodies on this copy, so the
+// kernels of eager launches carry nothing of it.
+__device__ inline StepParams graph_params(const StepParams &p) {
+    StepParams q = p;
+    const GraphTab *g = p.gtab;
+    const double *s = g->s + p.goff;
+    q.s_n = s[0];
+    q.s_n2 = s[1];
+    q.s_n3 = s[2];
+    q.s_n4 = s[3];
+    q.rec.col += g->t0;
+    q.gtab = nullptr;
+    return q;
+}
+
 // Receivers at node x of a row whose CSR entries are [rb, re): record the
 // fields of the pre-collision state g.
 template <typename T, int Q>

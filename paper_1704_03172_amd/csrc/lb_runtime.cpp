@@ -91,6 +91,7 @@ struct Layout {
     size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0, misfit = 0;
     size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, ring = 0, total = 0;
     size_t ckpt = 0, seg = 0, lam[2] = {0, 0};
+    size_t gtab = 0;
 };
 
 Layout make_layout(const lb_grid_desc *d) {
@@ -114,6 +115,7 @@ Layout make_layout(const lb_grid_desc *d) {
     L.partial = take((size_t)L.nblocks * 8);
     L.scratch = take(256);
     L.misfit = take((size_t)lbw::kMisfitMaxBlocks * 8);
+    L.gtab = take(sizeof(lbw::GraphTab));
     if (d->patch_enable) {
         PatchGeom g = patch_geom(d);
         const int64_t nf = (int64_t)g.nxf * g.nyf;
@@ -186,6 +188,20 @@ struct lb_grid {
     std::vector<char> ckpt_pre;    // slot holds a pre-collision state
     bool ckpt_valid = false;       // checkpoints describe the run since time 0
     bool state_lost = false;       // an adjoint overwrote the forward state
+    // graph replay of lb_step_n (lb_set_graph): chunks of graph_k steps
+    int32_t graph_k = 0;
+    int64_t gen = 0;               // bumped by every call that changes what a launch takes
+    int64_t graph_base = -1;       // while capturing: the chunk's first time (else -1)
+    lbw::GraphTab *gtab = nullptr; // the chunk table in the workspace
+    struct Cached {
+        hipGraphExec_t exec = nullptr;
+        int64_t gen = -1;
+        int flips = 0;             // buffer swaps of the chunk
+    } gcache[2];                   // by the buffer holding the chunk's first state
+    ~lb_grid() {
+        for (auto &c : gcache)
+            if (c.exec) hipGraphExecDestroy(c.exec);
+    }
 };
 
 namespace {
@@ -228,6 +244,17 @@ StepParams base_params(const lb_grid *h, const Lattice &g, bool is_main) {
     return p;
 }
 
+// While a chunk is captured for replay: point the launch at the chunk table
+// and make its times relative to the chunk's first time, which is returned
+// (0 outside a capture).
+int64_t graph_time(const lb_grid *h, StepParams &p, int64_t col) {
+    if (h->graph_base < 0) return 0;
+    p.gtab = h->gtab;
+    p.goff = (int32_t)(col - h->graph_base - 1);
+    p.rec.col -= h->graph_base;
+    return h->graph_base;
+}
+
 void attach_receivers(const lb_grid *h, const Lattice &g, StepParams &p, int64_t col) {
     if (!g.has_rec || h->nrec == 0) return;
     p.rec.row_ptr = g.rrow;
@@ -254,6 +281,7 @@ int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, 
     if (is_main) p.s_n = source_at(h, col);
     if (record) attach_receivers(h, g, p, col);
     if (sum) p.partial = h->partial;
+    const int64_t base = graph_time(h, p, col);
     if (is_main && h->patch) {   // keep g(col) on the ring line: snapshot of time col
         p.snap = snap_buffer(h, col);
         p.snap_x0 = h->geom.X0;
@@ -276,7 +304,7 @@ int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, 
     LB_TRY(h, lbw::launch_step(h->storage, p, pull, h->stream));
     if (sum) {
         const int64_t nb = lbw::step_blocks(h->storage, g.nx, g.ny, pull);
-        LB_TRY(h, lbw::launch_sum_finalize(h->partial, nb, h->sum_rho + col, h->stream));
+        LB_TRY(h, lbw::launch_sum_finalize(h->partial, nb, h->sum_rho + (col - base), p.gtab, h->stream));
     }
     g.cur = 1 - g.cur;
     g.prev_pre = pull ? 0 : 1;
@@ -629,6 +657,7 @@ int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes, vo
     m.rslot = (int32_t *)(h->ws + L.rslot);
     h->partial = (double *)(h->ws + L.partial);
     h->scratch = (int32_t *)(h->ws + L.scratch);
+    h->gtab = (lbw::GraphTab *)(h->ws + L.gtab);
     size_t zero_bytes = L.pop[1] + (size_t)h->q * L.pstride * h->ssize;   // both buffers
     if (d->patch_enable) {
         h->patch = true;
@@ -699,6 +728,7 @@ int lb_set_state_fine(lb_grid *h, const void *rho, const void *jx, const void *j
 
 int lb_set_source(lb_grid *h, int32_t x, int32_t y, const double *wavelet, int64_t nt) {
     if (!h) return LB_E_INVALID;
+    ++h->gen;   // cached graphs of lb_step_n are stale
     if (h->sticky) return h->sticky;
     if (nt < 0 || (nt > 0 && !wavelet)) return LB_E_INVALID;
     if (nt == 0) {
@@ -723,6 +753,7 @@ int lb_set_source(lb_grid *h, int32_t x, int32_t y, const double *wavelet, int64
 
 int lb_record(lb_grid *h, const int32_t *rxy, int32_t nrec, void *d_traces, uint32_t what) {
     if (!h) return LB_E_INVALID;
+    ++h->gen;   // cached graphs of lb_step_n are stale
     if (h->sticky) return h->sticky;
     if (nrec == 0) {
         h->nrec = 0;
@@ -755,6 +786,7 @@ int lb_record(lb_grid *h, const int32_t *rxy, int32_t nrec, void *d_traces, uint
 
 int lb_record_sum_rho(lb_grid *h, double *d_sum) {
     if (!h) return LB_E_INVALID;
+    ++h->gen;   // cached graphs of lb_step_n are stale
     if (h->patch && d_sum) return LB_E_UNSUPPORTED;
     h->sum_rho = d_sum;
     return LB_OK;
@@ -781,6 +813,10 @@ int blocked_max(const lb_grid *h) {
 // kernel's).
 int blocked_steps(const lb_grid *h, int64_t left) {
     if (h->patch || h->sum_rho) return 1;
+    if (h->graph_base >= 0) {   // a captured chunk: the graph entry kernels' one count, else one step
+        const int g = lbw::stepn_graph_steps(h->storage, h->q, lbw::step_kind(h->coll), h->d.nx);
+        return std::min(g, blocked_max(h)) == g && left - 1 >= g ? g : 1;
+    }
     int ns = blocked_max(h);
     ns = (int)std::min<int64_t>(ns, left - 1);
     if (h->ckpt_valid)
@@ -811,10 +847,75 @@ int blocked_launch(lb_grid *h, int ns) {
     for (int k = 0; k < 4; ++k) p.s_more[k] = source_at(h, col + 4 + k);
     p.nrun = ns;
     if (recording(h)) attach_receivers(h, g, p, col);
+    graph_time(h, p, col);
     LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));
     g.cur = 1 - g.cur;
     g.prev_pre = 0;
     h->t = col + ns - 1;
+    return LB_OK;
+}
+
+// Whether lb_step_n may replay graphs now: enabled, no patch (three
+// launches per coarse step with interface work), no checkpoints (their
+// saves depend on the time) and a stream of the caller's (the null stream
+// cannot be captured).
+bool graph_ok(const lb_grid *h) {
+    return h->graph_k > 0 && !h->patch && !h->ckpt_valid && h->stream != nullptr;
+}
+
+// One chunk of graph_k steps, replayed from a captured graph.  The chunk's
+// launches are those of a call of graph_k steps (blocked launches of at most
+// stepn_max steps, the last launch one step) with their times relative to
+// the chunk's first time t0; before each replay one small launch writes t0
+// and the chunk's source amplitudes into the chunk table.  One graph thus
+// serves every chunk that starts from the same buffer; it is captured on
+// first use and again after any call that changes what the launches take.
+int graph_chunk(lb_grid *h) {
+    const int64_t t0 = h->t;
+    const int cur0 = h->main.cur;
+    lb_grid::Cached &c = h->gcache[cur0];
+    lbw::GraphTab tab;
+    tab.t0 = t0;
+    for (int k = 0; k < h->graph_k; ++k) tab.s[k] = source_at(h, t0 + 1 + k);
+    LB_TRY(h, lbw::launch_graph_prime(h->gtab, tab, h->stream));
+    if (!c.exec || c.gen != h->gen) {
+        if (c.exec) {
+            LB_TRY(h, hipGraphExecDestroy(c.exec));
+            c.exec = nullptr;
+        }
+        // the launch functions advance the host state as if the launches
+        // ran; it is put back afterwards and advanced once for the replay
+        LB_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        h->graph_base = t0;
+        int rc = LB_OK;
+        for (int64_t k = 0; k < h->graph_k && rc == LB_OK;) {
+            const int ns = blocked_steps(h, h->graph_k - k);
+            rc = ns > 1 ? blocked_launch(h, ns) : one_step(h);
+            k += ns;
+        }
+        h->graph_base = -1;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(h->stream, &graph);
+        const int flips = h->main.cur != cur0;
+        h->t = t0;
+        h->main.cur = cur0;
+        if (rc != LB_OK || ec != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return rc != LB_OK ? rc : hip_fail(h, ec);
+        }
+        const hipError_t ei = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            c.exec = nullptr;
+            return hip_fail(h, ei);
+        }
+        c.gen = h->gen;
+        c.flips = flips;
+    }
+    LB_TRY(h, hipGraphLaunch(c.exec, h->stream));
+    h->t = t0 + h->graph_k;
+    if (c.flips) h->main.cur ^= 1;
+    h->main.prev_pre = 0;
     return LB_OK;
 }
 
@@ -828,6 +929,11 @@ int lb_step_n(lb_grid *h, int64_t n) {
     int rc;
     if (!h->collided && (rc = initial_collision(h))) return rc;
     for (int64_t k = 0; k < n;) {
+        if (graph_ok(h) && n - k >= h->graph_k) {
+            if ((rc = graph_chunk(h))) return rc;
+            k += h->graph_k;
+            continue;
+        }
         const int ns = blocked_steps(h, n - k);
         if (ns > 1) {
             if ((rc = blocked_launch(h, ns))) return rc;
@@ -836,6 +942,18 @@ int lb_step_n(lb_grid *h, int64_t n) {
         }
         k += ns;
     }
+    return LB_OK;
+}
+
+static_assert(LB_GRAPH_MAX_STEPS == lbw::kGraphMaxSteps, "the chunk table holds the largest chunk");
+
+int lb_set_graph(lb_grid *h, int32_t steps) {
+    if (!h) return LB_E_INVALID;
+    if (h->sticky) return h->sticky;
+    if (steps != 0 && (steps < 2 || steps > lbw::kGraphMaxSteps)) return LB_E_RANGE;
+    if (steps != 0 && (h->patch || h->stream == nullptr)) return LB_E_UNSUPPORTED;
+    h->graph_k = steps;
+    ++h->gen;
     return LB_OK;
 }
 
@@ -949,6 +1067,7 @@ int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_
 
 int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
     if (!h || !d_res || !d_grad) return LB_E_INVALID;
+    ++h->gen;   // cached graphs of lb_step_n are stale
     if (h->sticky) return h->sticky;
     if (h->patch) return LB_E_UNSUPPORTED;
     if (h->d.ckpt_every <= 0) return LB_E_STATE;

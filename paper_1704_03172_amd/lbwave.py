@@ -27,7 +27,7 @@ COLLISION = {"bgk": 0, "mrt": 1}
 EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_blocked_steps", "lb_workspace_bytes",
            "lb_create_grid", "lb_destroy_grid", "lb_set_medium",
            "lb_set_medium_fine", "lb_set_state", "lb_set_state_fine",
-           "lb_set_source", "lb_record", "lb_record_sum_rho", "lb_step_n",
+           "lb_set_source", "lb_record", "lb_record_sum_rho", "lb_step_n", "lb_set_graph",
            "lb_get_time", "lb_get_field", "lb_get_field_fine",
            "lb_state_bytes", "lb_get_state", "lb_set_raw_state", "lb_sync",
            "lb_status_string", "lb_device_copy",
@@ -105,6 +105,7 @@ def lib():
         "lb_record": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, vp, u32]),
         "lb_record_sum_rho": (ctypes.c_int, [vp, vp]),
         "lb_step_n": (ctypes.c_int, [vp, i64]),
+        "lb_set_graph": (ctypes.c_int, [vp, ctypes.c_int32]),
         "lb_get_time": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
         "lb_get_field": (ctypes.c_int, [vp, u32, vp]),
         "lb_get_field_fine": (ctypes.c_int, [vp, u32, vp]),
@@ -301,6 +302,11 @@ class Grid:
 
     def step(self, n=1):
         _check(lib().lb_step_n(self.handle, int(n)), "lb_step_n")
+
+    def set_graph(self, steps):
+        """Replay whole chunks of `steps` steps of each step() call from a
+        captured HIP graph (0: off)."""
+        _check(lib().lb_set_graph(self.handle, int(steps)), "lb_set_graph")
 
     @property
     def time(self):
