@@ -141,16 +141,19 @@ def refined_variant(torch, lbwave, inputs, coarse_steps=300):
         "fine_nodes": nf, "ms_per_coarse_step": round(tv / coarse_steps * 1e3, 4)}}
 
 
-def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
+def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55, tape=True):
     """Gradient of the summed trace misfit of `nshots` shots w.r.t. c^2:
-    per shot a checkpointed forward run (FP32) and lb_adjoint; FP64
-    gradient sum.  Observed data come from forward runs in the true medium
-    (not timed)."""
+    per shot a forward run (FP32) and lb_adjoint; FP64 gradient sum.  With
+    `tape` the forward run keeps every time's rho (nsteps + 1 fields in
+    HBM) and the backward steps read it; else the forward run keeps a
+    checkpoint every K steps and lb_adjoint recomputes each segment.
+    Observed data come from forward runs in the true medium (not timed)."""
     wl = inputs.adjoint_workload(n=n, nshots=nshots, nsteps=nsteps)
     rec = wl["receivers"]
+    mode = dict(rho_tape=1) if tape else dict(ckpt_every=K, ckpt_capacity=nsteps // K + 1)
     g = lbwave.Grid(n, n, precision="f32", sponge_width=wl["sponge_width"],
                     sponge_sigma_max=wl["sponge_sigma_max"], trace_capacity=nsteps + 1,
-                    max_receivers=len(rec), ckpt_every=K, ckpt_capacity=nsteps // K + 1)
+                    max_receivers=len(rec), **mode)
     obs = []
     g.set_medium(wl["c2_true"])
     for src in wl["sources"]:
@@ -186,22 +189,25 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55):
     finite = bool(torch.isfinite(grad).all().item())
     g.close()
     N = n * n
-    # the recompute writes each step's rho, through the short-segment kernel
-    # (steps_per_launch=4 gives its count)
-    ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32", steps_per_launch=4)
-    return {"workload": "%d shots, %dx%d, %d steps, checkpoints every %d, FP32 state, FP64 gradient"
-                        % (nshots, n, n, nsteps, K),
-            "seconds_total": round(wall, 3), "ms_per_shot": round(wall / nshots * 1e3, 2),
-            "forward_ms_per_shot": round(t_fwd / nshots * 1e3, 2),
-            "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
-            # algorithmic bytes per node and step of the adjoint phase: the
-            # blocked recompute (44 B per ns-step launch plus the 4-byte rho
-            # field of each step) and the two-step adjoint launch (lambda in
-            # and out, c^2 and the FP64 gradient read and written once per two
-            # steps, rho of both: 68 B per two steps)
-            "adjoint_phase_GB_s": round((44.0 / ns_rec + 4 + 68 / 2.0) * N * nsteps / (t_adj / nshots) / 1e9, 1),
-            "recompute_steps_per_launch": ns_rec,
-            "misfit": float(phi.item()), "gradient_finite": finite}
+    out = {"workload": "%d shots, %dx%d, %d steps, %s, FP32 state, FP64 gradient"
+                       % (nshots, n, n, nsteps, "forward rho of every time kept (%.1f GB)"
+                          % ((nsteps + 1) * N * 4 / 1e9) if tape else "checkpoints every %d" % K),
+           "seconds_total": round(wall, 3), "ms_per_shot": round(wall / nshots * 1e3, 2),
+           "forward_ms_per_shot": round(t_fwd / nshots * 1e3, 2),
+           "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
+           "misfit": float(phi.item()), "gradient_finite": finite}
+    if tape:
+        # algorithmic bytes per node and step of the adjoint phase: the
+        # two-step adjoint launch (lambda in and out, c^2 and the FP64
+        # gradient read and written once per two steps, rho of both: 68 B)
+        out["adjoint_phase_GB_s"] = round(68 / 2.0 * N * nsteps / (t_adj / nshots) / 1e9, 1)
+    else:
+        # plus the recompute (44 B per ns-step launch and the 4-byte rho
+        # field of each step), through the rho-writing kernel
+        ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32", steps_per_launch=4)
+        out["adjoint_phase_GB_s"] = round((44.0 / ns_rec + 4 + 68 / 2.0) * N * nsteps / (t_adj / nshots) / 1e9, 1)
+        out["recompute_steps_per_launch"] = ns_rec
+    return out
 
 
 KERNEL_SOURCES = ("lb_blocked.h", "lb_blocked_f32_q5.hip", "lb_node.h", "lb_internal.h")
@@ -443,6 +449,12 @@ def main():
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_bench(torch, lbwave, inputs, args.adj_n, args.adj_shots, args.adj_steps)
+        log("adjoint with the rho tape: %.1f ms per shot" % adjoint["ms_per_shot"])
+        torch.cuda.empty_cache()
+        adjoint["checkpointed"] = adjoint_bench(torch, lbwave, inputs, args.adj_n, max(1, args.adj_shots // 4),
+                                                args.adj_steps, tape=False)
+        log("adjoint with checkpoints: %.1f ms per shot" % adjoint["checkpointed"]["ms_per_shot"])
+        torch.cuda.empty_cache()
 
     serving = None
     if not args.no_serving:

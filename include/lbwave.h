@@ -122,6 +122,13 @@ typedef struct lb_grid lb_grid;
  *                  1 .. 8: at most that many steps per launch (a launch
  *                  takes 1 .. 4 steps, or the six or eight offered).
  *   nbatch         independent shots sharing the grid shape (must be 1).
+ *   rho_tape       1: lb_step_n also keeps the pre-collision rho of every
+ *                  time 0 .. trace_capacity - 1 of the run since lb_set_state
+ *                  (the workspace grows by trace_capacity rho fields), and
+ *                  lb_adjoint reads it instead of recomputing segments from
+ *                  checkpoints (no ckpt_every needed).  Steps are taken up to
+ *                  four per launch (the kernels that write rho).  Not with a
+ *                  patch.  0: off.
  */
 typedef struct {
     int32_t nx, ny;
@@ -144,6 +151,8 @@ typedef struct {
     int32_t ckpt_every;
     int32_t ckpt_capacity;
     int32_t steps_per_launch;
+    int32_t rho_tape;
+    int32_t _pad1;
 } lb_grid_desc;
 
 /* Fill *d with defaults: 64 x 64 D2Q5 BGK FP32, tau = 1/2, MRT rates
@@ -327,13 +336,15 @@ int lb_trace_misfit_static(const void *d_traces, const void *d_obs, void *d_res,
  * and the dependence of the initial equilibrium on the weights).
  * d_res [nrec][trace_capacity] holds dL/dp_r(n) for n = 0..nt (for the L2
  * misfit, the residual of lb_misfit); d_grad receives dL/dc^2 [ny][nx] in
- * FP64.  Needs ckpt_every > 0, receivers recorded, no patch, and a forward
- * run of exactly nt steps from lb_set_state (or the rest state) with the
- * same medium and source.  The forward segments are recomputed from the
- * checkpoints (as many steps per launch as lb_step_n takes; the gradient is
- * the same bits whatever steps_per_launch says); afterwards the population
- * state is no longer the forward state, so stepping again needs
- * lb_set_state or lb_set_raw_state first. */
+ * FP64.  Needs rho_tape = 1 or ckpt_every > 0, receivers recorded, no
+ * patch, and a forward run of exactly nt steps from lb_set_state (or the
+ * rest state) with the same medium and source.  With the tape the backward
+ * steps read the forward rho it holds and the population state is left as
+ * it was.  Otherwise the forward segments are recomputed from the
+ * checkpoints (as many steps per launch as lb_step_n takes), and afterwards
+ * the population state is no longer the forward state, so stepping again
+ * needs lb_set_state or lb_set_raw_state first.  The gradient is the same
+ * bits either way and whatever steps_per_launch says. */
 int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad);
 
 /* Wait for all work enqueued by the handle; returns the sticky error. */

@@ -67,6 +67,9 @@ int validate(const lb_grid_desc *d) {
     if (d->ckpt_every > 0 && d->ckpt_capacity < 1) return LB_E_RANGE;
     if (d->ckpt_every > 0 && d->patch_enable) return LB_E_UNSUPPORTED;
     if (d->steps_per_launch < 0 || d->steps_per_launch > 8) return LB_E_RANGE;
+    if (d->rho_tape != 0 && d->rho_tape != 1) return LB_E_RANGE;
+    if (d->rho_tape && d->patch_enable) return LB_E_UNSUPPORTED;
+    if (d->rho_tape && d->trace_capacity < 1) return LB_E_RANGE;
     if (d->patch_enable) {
         if (d->lattice != LB_D2Q5 || d->patch_refine != 2) return LB_E_UNSUPPORTED;
         if (!omega_is_two(d)) return LB_E_UNSUPPORTED;
@@ -91,7 +94,7 @@ struct Layout {
     size_t frow = 0, fxs = 0, fslot = 0, partial = 0, scratch = 0, misfit = 0;
     size_t fpop[2] = {0, 0}, fc2 = 0, snap = 0, ring = 0, total = 0;
     size_t ckpt = 0, seg = 0, lam[2] = {0, 0};
-    size_t gtab = 0;
+    size_t gtab = 0, tape = 0;
 };
 
 Layout make_layout(const lb_grid_desc *d) {
@@ -132,9 +135,12 @@ Layout make_layout(const lb_grid_desc *d) {
     if (d->ckpt_every > 0) {
         L.ckpt = take((size_t)d->ckpt_capacity * d->lattice * L.pstride * ss);
         L.seg = take((size_t)d->ckpt_every * n * ts);
+    }
+    if (d->ckpt_every > 0 || d->rho_tape) {
         L.lam[0] = take((size_t)d->lattice * L.pstride * ts);
         L.lam[1] = take((size_t)d->lattice * L.pstride * ts);
     }
+    if (d->rho_tape) L.tape = take((size_t)d->trace_capacity * n * ts);
     L.total = off;
     return L;
 }
@@ -187,6 +193,8 @@ struct lb_grid {
     void *lam[2] = {nullptr, nullptr};
     std::vector<char> ckpt_pre;    // slot holds a pre-collision state
     bool ckpt_valid = false;       // checkpoints describe the run since time 0
+    void *tape = nullptr;          // [trace_capacity][ny][nx] pre-collision rho of each time
+    bool tape_valid = false;       // the tape holds times 0 .. t of the run since time 0
     bool state_lost = false;       // an adjoint overwrote the forward state
     // graph replay of lb_step_n (lb_set_graph): chunks of graph_k steps
     int32_t graph_k = 0;
@@ -255,6 +263,11 @@ int64_t graph_time(const lb_grid *h, StepParams &p, int64_t col) {
     return h->graph_base;
 }
 
+// The tape's rho field of time n.
+void *tape_field(const lb_grid *h, int64_t n) {
+    return (char *)h->tape + (size_t)n * h->main.nx * h->main.ny * h->tsize;
+}
+
 void attach_receivers(const lb_grid *h, const Lattice &g, StepParams &p, int64_t col) {
     if (!g.has_rec || h->nrec == 0) return;
     p.rec.row_ptr = g.rrow;
@@ -281,6 +294,7 @@ int launch_update(lb_grid *h, Lattice &g, bool is_main, bool pull, int64_t col, 
     if (is_main) p.s_n = source_at(h, col);
     if (record) attach_receivers(h, g, p, col);
     if (sum) p.partial = h->partial;
+    if (is_main && h->tape_valid) p.rho_out = tape_field(h, col);
     const int64_t base = graph_time(h, p, col);
     if (is_main && h->patch) {   // keep g(col) on the ring line: snapshot of time col
         p.snap = snap_buffer(h, col);
@@ -389,6 +403,7 @@ int initial_collision(lb_grid *h) {
         h->ckpt_valid = h->t == 0;
         if (h->ckpt_valid && (rc = save_checkpoint(h, 0, true))) return rc;
     }
+    h->tape_valid = h->tape != nullptr && h->t == 0;   // this launch writes rho(0)
     if ((rc = launch_update(h, h->main, true, false, h->t, rec, sum))) return rc;
     if (h->patch) {
         // fine state of time 0 with its outer ring from the coarse state
@@ -494,6 +509,7 @@ int set_state_impl(lb_grid *h, Lattice &g, const void *rho, const void *jx, cons
         h->collided = false;
         h->state_lost = false;
         h->ckpt_valid = false;
+        h->tape_valid = false;
         if (h->patch) {   // the fine grid restarts at rest (lb_set_state_fine may follow)
             Lattice &f = h->fine;
             f.cur = 0;
@@ -678,10 +694,13 @@ int lb_create_grid(const lb_grid_desc *d, void *d_workspace, size_t ws_bytes, vo
     if (d->ckpt_every > 0) {
         h->ckpt = h->ws + L.ckpt;
         h->seg = h->ws + L.seg;
-        h->lam[0] = h->ws + L.lam[0];
-        h->lam[1] = h->ws + L.lam[1];
         h->ckpt_pre.assign((size_t)d->ckpt_capacity, 0);
     }
+    if (d->ckpt_every > 0 || d->rho_tape) {
+        h->lam[0] = h->ws + L.lam[0];
+        h->lam[1] = h->ws + L.lam[1];
+    }
+    if (d->rho_tape) h->tape = h->ws + L.tape;
     // the state starts at rest: zero both population buffers of each grid
     hipError_t e = lbw::launch_fill_zero(m.pop[0], (int64_t)zero_bytes, h->stream);
     if (e == hipSuccess && h->patch)
@@ -801,6 +820,9 @@ int blocked_max(const lb_grid *h) {
     int ns = lbw::stepn_max_grid(h->storage, h->q, sk, h->d.nx, h->d.ny);
     if (h->d.steps_per_launch > 0)
         ns = lbw::stepn_round(h->storage, h->q, sk, h->d.nx, h->d.ny, std::min(ns, h->d.steps_per_launch));
+    if (h->tape)   // the kernels that also write rho take up to stepn_max steps
+        ns = lbw::stepn_round(h->storage, h->q, sk, h->d.nx, h->d.ny,
+                              std::min(ns, lbw::stepn_max(h->storage, h->q, h->d.collision)));
     return ns;
 }
 
@@ -847,6 +869,10 @@ int blocked_launch(lb_grid *h, int ns) {
     for (int k = 0; k < 4; ++k) p.s_more[k] = source_at(h, col + 4 + k);
     p.nrun = ns;
     if (recording(h)) attach_receivers(h, g, p, col);
+    if (h->tape_valid) {   // rho of times col .. col + ns - 1
+        p.rho_out = tape_field(h, col);
+        p.rho_stride = (int64_t)g.nx * g.ny;
+    }
     graph_time(h, p, col);
     LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));
     g.cur = 1 - g.cur;
@@ -860,7 +886,7 @@ int blocked_launch(lb_grid *h, int ns) {
 // saves depend on the time) and a stream of the caller's (the null stream
 // cannot be captured).
 bool graph_ok(const lb_grid *h) {
-    return h->graph_k > 0 && !h->patch && !h->ckpt_valid && h->stream != nullptr;
+    return h->graph_k > 0 && !h->patch && !h->ckpt_valid && !h->tape && h->stream != nullptr;
 }
 
 // One chunk of graph_k steps, replayed from a captured graph.  The chunk's
@@ -924,7 +950,9 @@ int lb_step_n(lb_grid *h, int64_t n) {
     if (h->sticky) return h->sticky;
     if (n < 0) return LB_E_RANGE;
     if (!h->main.medium || (h->patch && !h->fine.medium) || h->state_lost) return LB_E_STATE;
-    if ((recording(h) || h->sum_rho) && h->t + n >= h->d.trace_capacity) return LB_E_RANGE;
+    if ((recording(h) || h->sum_rho || h->tape_valid || (h->tape && !h->collided && h->t == 0)) &&
+        h->t + n >= h->d.trace_capacity)
+        return LB_E_RANGE;
     if (h->d.ckpt_every > 0 && (h->t + n) / h->d.ckpt_every >= h->d.ckpt_capacity) return LB_E_RANGE;
     int rc;
     if (!h->collided && (rc = initial_collision(h))) return rc;
@@ -997,8 +1025,13 @@ int lb_get_state(lb_grid *h, void *d_out) {
     hd.main_prev_pre = h->main.prev_pre;
     hd.fine_prev_pre = h->fine.prev_pre;
     hd.bytes = lb_state_bytes(h);
+    // the whole 256-byte header, zero past the fields, so that equal states
+    // give equal blobs
+    static_assert(sizeof(StateHeader) <= 256, "the header region holds the header");
+    unsigned char head[256] = {};
+    std::memcpy(head, &hd, sizeof(hd));
     char *o = (char *)d_out;
-    LB_TRY(h, hipMemcpyAsync(o, &hd, sizeof(hd), hipMemcpyHostToDevice, h->stream));
+    LB_TRY(h, hipMemcpyAsync(o, head, sizeof(head), hipMemcpyHostToDevice, h->stream));
     size_t off = 256;
     const size_t mb = (size_t)h->q * h->main.pstride * h->ssize;
     LB_TRY(h, hipMemcpyAsync(o + off, h->main.curp(), mb, hipMemcpyDeviceToDevice, h->stream));
@@ -1040,6 +1073,7 @@ int lb_set_raw_state(lb_grid *h, const void *d_in) {
     h->collided = hd.collided != 0;
     h->state_lost = false;
     h->ckpt_valid = false;       // checkpoints of another run do not apply
+    h->tape_valid = false;
     h->main.prev_pre = hd.main_prev_pre;
     h->fine.prev_pre = hd.fine_prev_pre;
     return LB_OK;
@@ -1065,15 +1099,45 @@ int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_
                               (double *)d_workspace, (hipStream_t)stream) == hipSuccess ? LB_OK : LB_E_HIP;
 }
 
+// Backward steps n = b, b - 1, .., a of the adjoint, the forward rho of time
+// n at rho_base + (n - a) fields; two steps per launch where both lie in
+// [a, b] (and not at the terminal time nt).  cur_lam: the lambda buffer
+// holding lambda(b + 1), updated.
+int adjoint_backward(lb_grid *h, lbw::AdjointParams &ap, char *rho_base, int64_t a, int64_t b, int64_t nt,
+                     int &cur_lam) {
+    const size_t field = (size_t)h->main.nx * h->main.ny * h->tsize;
+    for (int64_t n = b; n >= a;) {
+        ap.rho = rho_base + (size_t)(n - a) * field;
+        ap.terminal = n == nt;
+        ap.initial = n == 0;
+        ap.lam_next = h->lam[cur_lam];
+        ap.lam = h->lam[1 - cur_lam];
+        ap.s_n = source_at(h, n);
+        ap.rec.col = n;
+        if (n != nt && n - 1 >= a && blocked_max(h) >= 2) {
+            ap.rho_prev = rho_base + (size_t)(n - 1 - a) * field;
+            ap.s_prev = source_at(h, n - 1);
+            ap.initial_prev = n - 1 == 0;
+            LB_TRY(h, lbw::launch_adjoint2(h->storage, ap, h->stream));
+            n -= 2;
+        } else {
+            LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
+            n -= 1;
+        }
+        cur_lam = 1 - cur_lam;
+    }
+    return LB_OK;
+}
+
 int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
     if (!h || !d_res || !d_grad) return LB_E_INVALID;
     ++h->gen;   // cached graphs of lb_step_n are stale
     if (h->sticky) return h->sticky;
     if (h->patch) return LB_E_UNSUPPORTED;
-    if (h->d.ckpt_every <= 0) return LB_E_STATE;
-    if (!h->collided || !h->ckpt_valid || h->state_lost || nt != h->t) return LB_E_STATE;
+    const bool tape = h->tape_valid;   // else segments recomputed from checkpoints
+    if (!tape && h->d.ckpt_every <= 0) return LB_E_STATE;
+    if (!h->collided || !(tape || h->ckpt_valid) || h->state_lost || nt != h->t) return LB_E_STATE;
     if (!recording(h)) return LB_E_STATE;
-    const int64_t K = h->d.ckpt_every;
     Lattice &g = h->main;
     const int64_t n_nodes = (int64_t)g.nx * g.ny;
     const size_t tsz = h->tsize;
@@ -1109,6 +1173,8 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
 
     LB_TRY(h, lbw::launch_fill_zero(d_grad, n_nodes * 8, h->stream));
     int cur_lam = 0;     // lam[cur_lam] holds lambda(n+1)
+    if (tape) return adjoint_backward(h, ap, (char *)h->tape, 0, nt, nt, cur_lam);
+    const int64_t K = h->d.ckpt_every;
     for (int64_t j = nt / K; j >= 0; --j) {
         const int64_t a = j * K, b = std::min(a + K - 1, nt);
         // restore the forward state that the launch of time a pulls from
@@ -1142,28 +1208,8 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
             g.cur = 1 - g.cur;
             m += ns;
         }
-        // backward through the segment, two steps per launch where both lie
-        // in it (and not at the terminal time)
-        for (int64_t n = b; n >= a;) {
-            ap.rho = (char *)h->seg + (size_t)(n - a) * n_nodes * tsz;
-            ap.terminal = n == nt;
-            ap.initial = n == 0;
-            ap.lam_next = h->lam[cur_lam];
-            ap.lam = h->lam[1 - cur_lam];
-            ap.s_n = source_at(h, n);
-            ap.rec.col = n;
-            if (n != nt && n - 1 >= a && blocked_max(h) >= 2) {
-                ap.rho_prev = (char *)h->seg + (size_t)(n - 1 - a) * n_nodes * tsz;
-                ap.s_prev = source_at(h, n - 1);
-                ap.initial_prev = n - 1 == 0;
-                LB_TRY(h, lbw::launch_adjoint2(h->storage, ap, h->stream));
-                n -= 2;
-            } else {
-                LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
-                n -= 1;
-            }
-            cur_lam = 1 - cur_lam;
-        }
+        int rc = adjoint_backward(h, ap, (char *)h->seg, a, b, nt, cur_lam);
+        if (rc) return rc;
     }
     h->state_lost = true;
     return LB_OK;

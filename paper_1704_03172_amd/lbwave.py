@@ -63,6 +63,7 @@ class Desc(ctypes.Structure):
         ("max_receivers", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32), ("ckpt_capacity", ctypes.c_int32),
         ("steps_per_launch", ctypes.c_int32),
+        ("rho_tape", ctypes.c_int32), ("_pad1", ctypes.c_int32),
     ]
 
 
@@ -148,7 +149,7 @@ def _check(code, what):
 def make_desc(nx, ny, lattice=5, collision="bgk", precision="f32", tau=0.5,
               s=None, ratio=0.25, sponge_width=0, sponge_sigma_max=0.0,
               patch=None, overlap_out=2, overlap_in=2, trace_capacity=0,
-              max_receivers=0, ckpt_every=0, ckpt_capacity=0, steps_per_launch=0):
+              max_receivers=0, ckpt_every=0, ckpt_capacity=0, steps_per_launch=0, rho_tape=0):
     d = Desc()
     lib().lb_default_desc(ctypes.byref(d))
     d.nx, d.ny = int(nx), int(ny)
@@ -171,6 +172,7 @@ def make_desc(nx, ny, lattice=5, collision="bgk", precision="f32", tau=0.5,
     d.ckpt_every = int(ckpt_every)
     d.ckpt_capacity = int(ckpt_capacity)
     d.steps_per_launch = int(steps_per_launch)
+    d.rho_tape = int(rho_tape)
     return d
 
 

@@ -53,7 +53,7 @@ def test_desc_layout_matches_c(lw):
     assert d.d2q9_ratio == 0.25 and d.sponge_width == 0 and d.sponge_sigma_max == 0.0
     assert (d.patch_enable, d.patch_refine, d.patch_overlap_out, d.patch_overlap_in) == (0, 2, 2, 2)
     assert d.trace_capacity == 0 and d.max_receivers == 0 and d.steps_per_launch == 0
-    assert ctypes.sizeof(lw.Desc) == 184
+    assert ctypes.sizeof(lw.Desc) == 192
 
 
 @pytest.mark.parametrize("kw,code", [

@@ -33,15 +33,18 @@ def make_case(nx=96, ny=64, q=5, collision="bgk", tau=0.5, s=None, N=150, seed=1
     return case
 
 
-def gpu_gradient(case, precision, K=16, c2=None, steps_per_launch=0):
+def gpu_gradient(case, precision, K=16, c2=None, steps_per_launch=0, tape=False, check_state=False):
+    """(misfit, gradient) from the GPU: checkpoints every K steps, or
+    (tape) the forward rho of every time kept and no checkpoints."""
     import torch
     from paper_1704_03172_amd import lbwave
     N = case["nsteps"]
+    ck = dict(rho_tape=1) if tape else dict(ckpt_every=K, ckpt_capacity=N // K + 1)
     g = lbwave.Grid(case["nx"], case["ny"], lattice=case["q"], collision=case["collision"],
                     precision=precision, tau=case["tau"], s=case["s"], ratio=case["ratio"],
                     sponge_width=case["sponge_width"], sponge_sigma_max=case["sponge_sigma_max"],
                     trace_capacity=N + 1, max_receivers=len(case["receivers"]),
-                    ckpt_every=K, ckpt_capacity=N // K + 1, steps_per_launch=steps_per_launch)
+                    steps_per_launch=steps_per_launch, **ck)
     g.set_medium(case["c2"] if c2 is None else c2)
     if "rho0" in case:
         g.set_state(case["rho0"], case["jx0"], case["jy0"])
@@ -50,8 +53,11 @@ def gpu_gradient(case, precision, K=16, c2=None, steps_per_launch=0):
     g.step(N)
     d_obs = torch.as_tensor(case["d_obs"], device="cuda")
     phi, res = g.misfit(d_obs, N)
+    before = g.get_state().clone() if check_state else None
     grad = g.adjoint(res, N)
     g.sync()
+    if check_state:   # the tape path leaves the forward state alone
+        assert torch.equal(before, g.get_state())
     out = float(phi.item()), grad.cpu().numpy()
     g.close()
     return out
@@ -92,6 +98,57 @@ def test_blocked_recompute_gives_the_same_gradient(precision, kw):
         a = gpu_gradient(case, precision, K=K, steps_per_launch=1)[1]
         b = gpu_gradient(case, precision, K=K)[1]
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("kw", [dict(), dict(tau=0.8), dict(collision="mrt", s=[1, 1, 1, 1.4, 1.7]),
+                                dict(q=9, collision="mrt", s=[1, 1, 1, 2, 2, 2, 1, 1, 2]), dict(state=False)])
+def test_rho_tape_gives_the_same_gradient(precision, kw):
+    """With the forward rho of every time kept (no checkpoints, no
+    recompute) the gradient is the same bits as with checkpoints and as with
+    one step per launch, and the forward state survives the adjoint."""
+    case = make_case(N=97, seed=6, **kw)
+    a = gpu_gradient(case, precision, K=16)[1]
+    b = gpu_gradient(case, precision, tape=True, check_state=True)[1]
+    c = gpu_gradient(case, precision, tape=True, steps_per_launch=1)[1]
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+
+
+def test_rho_tape_fp64_matches_oracle_adjoint():
+    case = make_case(q=9, collision="mrt", s=[1, 1, 1, 2, 2, 2, 1, 1, 2])
+    ref, phi_ref = ad.adjoint_gradient(case)
+    phi, grad = gpu_gradient(case, "f64", tape=True)
+    assert abs(phi - phi_ref) <= 1e-12 * abs(phi_ref)
+    err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    assert err < 1e-10, err
+
+
+def test_rho_tape_capacity_and_state():
+    """The tape holds times 0 .. trace_capacity - 1: a run past it is
+    refused before any launch; the adjoint needs the run since time 0."""
+    import torch
+    from paper_1704_03172_amd import lbwave
+    case = make_case(N=40, seed=2)
+    g = lbwave.Grid(case["nx"], case["ny"], precision="f32", rho_tape=1, trace_capacity=41,
+                    max_receivers=len(case["receivers"]), sponge_width=6, sponge_sigma_max=0.1)
+    g.set_medium(case["c2"])
+    g.set_state(case["rho0"], case["jx0"], case["jy0"])
+    g.record(case["receivers"])
+    with pytest.raises(lbwave.LBError) as e:
+        g.step(41)
+    assert e.value.code == -2
+    g.step(40)
+    d_obs = torch.zeros((len(case["receivers"]), 41), dtype=torch.float32, device="cuda")
+    res = g.misfit(d_obs, 40)[1]
+    with pytest.raises(lbwave.LBError) as e:
+        g.adjoint(res, 39)
+    assert e.value.code == -6
+    g.set_raw_state(g.get_state())   # a state of unknown history: no tape
+    with pytest.raises(lbwave.LBError) as e:
+        g.adjoint(res, 40)
+    assert e.value.code == -6
+    g.close()
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient():
