@@ -354,6 +354,25 @@ def pulse_variant(torch, lbwave, inputs):
                                        "steps": wl["nsteps"], "sum_rho_recorded": True}}
 
 
+def serving_run(torch, inputs, nreq, rate, seed=4):
+    """The seeded shot trace served by continuous batching and one shot per
+    launch, each under first-come and aged shortest-job-first admission."""
+    from paper_1704_03172_amd import serve
+    trace = inputs.serving_trace(nreq, rate, seed=seed)
+    out = {"requests": nreq, "rate_per_s": rate, "seed": seed}
+    for policy in ("fifo", "sjf"):
+        log("serving %d requests at %g/s, continuous batching (%s admission)" % (nreq, rate, policy))
+        srv = serve.ShotServer(64 << 30, 32, None, policy=policy)
+        _, out["batched_" + policy] = srv.run(trace, progress=nreq >= 500)
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
+        log("serving the same trace one shot per launch (%s admission)" % policy)
+        _, out["one_shot_per_launch_" + policy] = serve.run_sequential(trace, policy, progress=nreq >= 500)
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +390,8 @@ def main():
     ap.add_argument("--adj-shots", type=int, default=16)
     ap.add_argument("--adj-steps", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serving-protocol", action="store_true",
+                    help="serve the 1000-request trace at 50/s and the 200-request trace at 5/s")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -458,19 +479,14 @@ def main():
 
     serving = None
     if not args.no_serving:
-        from paper_1704_03172_amd import serve
-        trace = inputs.serving_trace(args.serve_requests, 50.0, seed=4)
-        serving = {"requests": args.serve_requests, "rate_per_s": 50.0, "seed": 4}
-        for policy in ("fifo", "sjf"):
-            log("serving %d requests at 50/s, continuous batching (%s admission)" % (args.serve_requests, policy))
-            srv = serve.ShotServer(64 << 30, 32, None, policy=policy)
-            _, serving["batched_" + policy] = srv.run(trace)
-            srv.close()
-            del srv
-            torch.cuda.empty_cache()
-        log("serving the same trace one shot per launch (FIFO)")
-        _, serving["one_shot_per_launch"] = serve.run_fifo(trace)
-        torch.cuda.empty_cache()
+        protocol = [(args.serve_requests, 50.0)]
+        if args.serving_protocol:   # the overloaded and the under-capacity traces
+            protocol = [(1000, 50.0), (200, 5.0)]
+        serving = {}
+        for nreq, rate in protocol:
+            serving["%d@%g" % (nreq, rate)] = serving_run(torch, inputs, nreq, rate)
+        if len(protocol) == 1:
+            serving = dict(serving["%d@%g" % protocol[0]], requests=protocol[0][0], rate_per_s=protocol[0][1])
 
     traffic = measured_traffic(nsl) if args.n == 4096 else None
     cpu = None

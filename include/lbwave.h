@@ -396,28 +396,45 @@ int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots,
 size_t lb_shot_workspace_bytes(const lb_batch *b, const lb_shot_desc *s);
 
 /* Admit a shot into a free slot: c2 [ny][nx] as for lb_set_medium (range
- * checked), wavelet S(n) for n < nt (host, copied), receivers rxy[nrec][2]
- * (host, copied), caller-owned device traces [nrec][nsteps + 1] of the
- * arithmetic type receiving p at every time.  Zeroes the state, performs
- * the collision of time 0 and records time 0.  *slot receives the slot
- * index.  LB_E_RANGE if no slot is free.  Synchronises the stream. */
+ * checked; a device array must be complete when the call is made), wavelet
+ * S(n) for n < nt (host, copied), receivers rxy[nrec][2] (host, copied),
+ * caller-owned device traces [nrec][nsteps + 1] of the arithmetic type
+ * receiving p at every time (complete before the call, as c2).  Zeroes the
+ * state, performs the collision of time 0 and records time 0.  The work
+ * runs on an upload stream of the executor, not on `stream`: the ticks in
+ * flight keep running, and the call waits only for this shot's uploads
+ * (and, when every free slot was freed by a recent lb_batch_remove_shot,
+ * for the ticks enqueued before that removal).  The next tick waits for
+ * the admission on the device.  *slot receives the slot index.  LB_E_RANGE
+ * if no slot is free. */
 int lb_batch_add_shot(lb_batch *b, const lb_shot_desc *s, void *d_ws,
                       size_t ws_bytes, const void *c2, lb_dtype t,
                       int on_device, const double *wavelet, int64_t nt,
                       const int32_t *rxy, void *d_traces, int32_t *slot);
 
-/* Retire a shot (finished or not) and free its slot; after the call the
- * library no longer touches the shot's workspace or traces.  Synchronises
- * the stream. */
+/* Retire a shot (finished or not) and free its slot; the ticks enqueued
+ * after the call no longer touch the shot's workspace or traces, and those
+ * enqueued before it do so only while the shot is unfinished (an
+ * unfinished shot is stopped in stream order).  Returns without waiting for
+ * the ticks: the caller frees the workspace and reads the traces once the
+ * work enqueued so far on `stream` has run (for a finished shot, once
+ * lb_batch_completed reports its last time).  */
 int lb_batch_remove_shot(lb_batch *b, int32_t slot);
 
 /* Enqueue k time steps for every active shot; shots that reach their last
- * time stop updating inside the tick.  Returns without waiting. */
+ * time stop updating inside the tick.  Returns without waiting.  Each tick
+ * advances every active shot by min(k, steps left). */
 int lb_batch_tick(lb_batch *b, int64_t k);
 
-/* Time reached by every slot (host array of max_shots; -1 for free slots).
- * Synchronises the stream. */
+/* Time every slot reaches once the enqueued ticks have run (host array of
+ * max_shots; -1 for free slots).  Returns without waiting. */
 int lb_batch_times(lb_batch *b, int64_t *t_out);
+
+/* Time every slot has reached on the device: that of the newest tick known
+ * to have completed (host array of max_shots; -1 for free slots and for
+ * shots no tick has completed since their admission).  Returns without
+ * waiting (it polls the ticks' completion events). */
+int lb_batch_completed(lb_batch *b, int64_t *t_out);
 
 /* Wait for all enqueued work; returns the sticky error. */
 int lb_batch_sync(lb_batch *b);

@@ -34,6 +34,7 @@ namespace {
 // so the result equals NS launches of the one-step kernel bit for bit.  Only
 // rows and columns the wave owns are recorded.
 constexpr int kT2Block = 256;
+
 constexpr int kT2Halo = 4;    // halo lanes per side
 
 template <typename S> struct Tb {
@@ -48,10 +49,23 @@ template <typename S> struct Tb {
 
 template <int V, typename S> struct LaneVec { typedef S type __attribute__((ext_vector_type(V), aligned(sizeof(S)))); };
 
+// The populations and c^2 live in global memory.  The walks' accesses say
+// so: a batched launch reads the arrays' addresses from memory as generic
+// pointers, whose accesses would otherwise take the flat path.
+template <typename U>
+using GlobalPtr = __attribute__((address_space(1))) U *;
+
 // Load with the ordinary cache policy (keep) or nontemporal.
 template <typename U>
 __device__ inline U ld_hint(const U *p, bool keep) {
-    return keep ? *p : __builtin_nontemporal_load(p);
+    const GlobalPtr<const U> g = (GlobalPtr<const U>)p;
+    return keep ? *g : __builtin_nontemporal_load(g);
+}
+
+// Nontemporal store to global memory.
+template <typename U>
+__device__ inline void st_nt(U v, U *p) {
+    __builtin_nontemporal_store(v, (GlobalPtr<U>)p);
 }
 
 // Element x of a row as a wave-uniform row pointer plus an unsigned 32-bit
@@ -396,7 +410,7 @@ __device__ __attribute__((always_inline)) inline void stepn_wave(const StepParam
                     rt t;
 #pragma unroll
                     for (int j = 0; j < V; ++j) t[j] = rhov[j];
-                    *at_lane<rt>(rr, xv) = t;
+                    *(GlobalPtr<rt>)at_lane<rt>(rr, xv) = t;
                 }
             } else {
 #pragma unroll
@@ -416,12 +430,12 @@ __device__ __attribute__((always_inline)) inline void stepn_wave(const StepParam
                             vt t;
 #pragma unroll
                             for (int j = 0; j < V; ++j) t[j] = S(po[i][j]);
-                            __builtin_nontemporal_store(t, at_lane<vt>(r, xv));
+                            st_nt(t, at_lane<vt>(r, xv));
                         }
                     } else {
 #pragma unroll
                         for (int j = 0; j < V; ++j)
-                            if (own[j]) __builtin_nontemporal_store(S(po[i][j]), r + xw[j]);
+                            if (own[j]) st_nt(S(po[i][j]), r + xw[j]);
                     }
                 }
             }
@@ -507,6 +521,22 @@ __device__ inline KernargParams rare_params() {
     return q;
 }
 
+// Where the marching walk reads the fields of its rarely taken branches:
+// the kernel arguments of a single-grid launch (RareKernarg), or the params
+// image of the wave's shot in global memory (a batched launch), through a
+// pointer hidden from the compiler for the same reason.
+struct RareKernarg {
+    __device__ KernargParams operator()() const { return rare_params(); }
+};
+struct RareGlobal {
+    const StepParams *img;
+    __device__ const StepParams *operator()() const {
+        const StepParams *q = img;
+        asm volatile("" : "+s"(q));
+        return q;
+    }
+};
+
 // One of eight arrays chosen at compile time.
 template <int I, typename A>
 __device__ inline A &pick8(A &a0, A &a1, A &a2, A &a3, A &a4, A &a5, A &a6, A &a7) {
@@ -514,9 +544,9 @@ __device__ inline A &pick8(A &a0, A &a1, A &a2, A &a3, A &a4, A &a5, A &a6, A &a
     else return pick4<I - 4>(a4, a5, a6, a7);
 }
 
-template <typename S, int Q, int KIND, int NS>
+template <typename S, int Q, int KIND, int NS, typename RARE>
 __device__ __attribute__((always_inline)) inline void march_wave(const StepParams &p, int wave,
-                                                                 typename Tr<S>::T *c2ring) {
+                                                                 typename Tr<S>::T *c2ring, RARE rare) {
     using T = typename Tr<S>::T;
     using M = March<S, Q, KIND, NS>;
     constexpr int V = MTb<S, NS>::V, H = MTb<S, NS>::H, OW = MTb<S, NS>::OW;
@@ -627,7 +657,7 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
             re = __builtin_amdgcn_readlane(rowv, m - NS + 1);
         }
         if (__builtin_expect(rb < re, 0)) {
-            const KernargParams q = rare_params();
+            const auto q = rare();
             Receivers rc;   // field by field: no copy constructor from this address space
             rc.row_ptr = q->rec.row_ptr;
             rc.xs = q->rec.xs;
@@ -654,7 +684,7 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
             collide<T, Q, KIND>(gj, cm[j], p.coll, pj[j], w);
         }
         if (__builtin_expect(wm == p.src_y, 0)) {
-            const KernargParams q = rare_params();
+            const auto q = rare();
             const double snv = st == 1 ? q->s_n : st == 2 ? q->s_n2 : st == 3 ? q->s_n3 : st == 4 ? q->s_n4
                                                                                         : q->s_more[(st - 5) & 3];
             const int sxs = q->src_x;
@@ -672,7 +702,7 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
         }
         const int dy = min(wm, ny - 1 - wm);
         if (__builtin_expect(strip_sponge || dy < L, 0)) {
-            const double smax = rare_params()->sponge_smax;
+            const double smax = rare()->sponge_smax;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const int d = min(dxw[j], dy);
@@ -691,7 +721,7 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
                     vt t;
 #pragma unroll
                     for (int j = 0; j < V; ++j) t[j] = to_store<S>(pj[j][i]);
-                    __builtin_nontemporal_store(t, at_lane<vt>(dst + i * p.pstride + ro, xv));
+                    st_nt(t, at_lane<vt>(dst + i * p.pstride + ro, xv));
                 }
             }
         } else {
@@ -739,7 +769,7 @@ __global__ __launch_bounds__(kT2Block) void k_stepn_march(StepParams p) {
     constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
     __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    march_wave<S, Q, KIND, NS>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib]);
+    march_wave<S, Q, KIND, NS>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib], RareKernarg());
 }
 
 template <typename S, int Q, int KIND, bool VEC, int NS, bool RHO>
@@ -778,6 +808,7 @@ void k_stepn_batch(BatchParams bp) {
         if (bp.wprefix[mid] <= w) lo = mid; else hi = mid - 1;
     }
     const int slot = bp.order[lo];
+    if (bp.img != nullptr && bp.img[slot].nrun > 0) return;   // the round's marching launch takes it
     const ShotState ss = bp.state[slot];
     if (!ss.active || ss.t >= ss.t_end) return;
     const ShotEntry &e = bp.table[slot];
@@ -808,6 +839,31 @@ void k_stepn_batch(BatchParams bp) {
     // rest (a shot's last launch, odd widths) the general one
     if (nrun == NS && e.nx % Tb<S>::V == 0) stepn_wave<S, Q, KIND, true, NS, true>(p, lw, NS);
     else stepn_wave<S, Q, KIND, false, NS, false>(p, lw, nrun);
+}
+
+// The batched marching launch: wave w belongs to the active shot a with
+// mprefix[a] <= w < mprefix[a+1] and walks that shot's grid with the params
+// image of the round (shots that sit the round out have no waves of use).
+template <typename S, int Q, int KIND, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn_march_batch(BatchParams bp, const StepParams *__restrict__ img) {
+    using T = typename Tr<S>::T;
+    constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
+    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
+    if (w >= bp.mprefix[bp.nact]) return;
+    int lo = 0, hi = bp.nact - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bp.mprefix[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int slot = __builtin_amdgcn_readfirstlane(bp.order[lo]);
+    const StepParams *q = img + slot;
+    if (q->nrun != NS) return;
+    // a copy in registers: read through q, the fields would be read again
+    // after every store of the walk (the compiler cannot tell them apart)
+    const StepParams pl = *q;
+    march_wave<S, Q, KIND, NS>(pl, (int)(w - bp.mprefix[lo]), c2ring[wib], RareGlobal{q});
 }
 
 // f(integral_constant<int, ns>()) for 2 <= ns <= the largest tn_max<S, Q, KIND>
@@ -940,6 +996,37 @@ hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hip
     });
 }
 
+template <typename S, int Q>
+hipError_t stepn_march_batch_launch(const BatchParams &bp, int64_t nwaves, hipStream_t s) {
+    const dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const int kind = step_kind(bp.coll);
+    auto launch = [&](auto kc) {
+        constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
+        if constexpr (MN > 0) {
+            hipLaunchKernelGGL((k_stepn_march_batch<S, Q, KK, MN>), grid, dim3(kT2Block), 0, s, bp,
+                               (const StepParams *)bp.img);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    };
+    return kind == 1 ? launch(std::integral_constant<int, 1>())
+         : kind == 2 ? launch(std::integral_constant<int, 2>()) : launch(std::integral_constant<int, 0>());
+}
+
+template <typename S, int Q>
+int64_t march_waves_of(int kind, int32_t nx, int32_t ny) {
+    auto waves = [&](auto kc) -> int64_t {
+        constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
+        if constexpr (MN > 0) {
+            if (!march_ok<S, Q, KK, MN>(nx, ny)) return 0;
+            return march_waves<S, Q, KK, MN>(nx, ny);
+        }
+        return 0;
+    };
+    return kind == 1 ? waves(std::integral_constant<int, 1>())
+         : kind == 2 ? waves(std::integral_constant<int, 2>()) : waves(std::integral_constant<int, 0>());
+}
+
 }  // namespace
 
 // One source per storage format and lattice instantiates the kernels with
@@ -951,6 +1038,12 @@ hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hip
     int march_steps_##NAME(int kind, int32_t nx, int32_t ny) {                                      \
         return march_grid<SS, QQ>(kind, nx, ny);                                                    \
     }                                                                                               \
+    hipError_t launch_stepn_march_batch_##NAME(const BatchParams &bp, int64_t nwaves, hipStream_t s) {   \
+        return stepn_march_batch_launch<SS, QQ>(bp, nwaves, s);                                     \
+    }                                                                                               \
+    int64_t march_waves_##NAME(int kind, int32_t nx, int32_t ny) {                                  \
+        return march_waves_of<SS, QQ>(kind, nx, ny);                                                \
+    }                                                                                               \
     hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s) { \
         return stepn_batch_launch<SS, QQ>(bp, ns, nwaves, s);                                       \
     }
@@ -958,7 +1051,9 @@ hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hip
 #define LBW_BLOCKED_DECL(NAME)                                                                      \
     hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s);                     \
     int march_steps_##NAME(int kind, int32_t nx, int32_t ny);                                       \
-    hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s);
+    hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s); \
+    hipError_t launch_stepn_march_batch_##NAME(const BatchParams &bp, int64_t nwaves, hipStream_t s);   \
+    int64_t march_waves_##NAME(int kind, int32_t nx, int32_t ny);
 LBW_BLOCKED_DECL(f32_q5)
 LBW_BLOCKED_DECL(f32_q9)
 LBW_BLOCKED_DECL(f64_q5)

@@ -24,6 +24,58 @@ __global__ __launch_bounds__(kAdvBlock) void k_batch_advance_n(ShotState *state,
     }
 }
 
+// Params images of a marching round (see launch_batch_march_prep).
+__global__ __launch_bounds__(kAdvBlock) void k_batch_march_prep(BatchParams bp, int q, int ns) {
+    const int a = blockIdx.x * kAdvBlock + threadIdx.x;
+    if (a >= bp.nact) return;
+    const int slot = bp.order[a];
+    const ShotState ss = bp.state[slot];
+    const ShotEntry &e = bp.table[slot];
+    StepParams p;
+    p.src = ss.cur ? e.pop1 : e.pop0;
+    p.dst = ss.cur ? e.pop0 : e.pop1;
+    p.c2 = e.c2;
+    p.nx = e.nx;
+    p.ny = e.ny;
+    p.pstride = e.pstride;
+    p.q = q;
+    p.coll = bp.coll;
+    p.sponge_width = e.sponge_width;
+    p.sponge_smax = e.sponge_smax;
+    p.src_x = e.src_x;
+    p.src_y = e.src_y;
+    const int64_t tn = ss.t + 1;
+    auto wv = [&](int64_t n) { return n < e.wavelet_len ? e.wavelet[n] : 0.0; };
+    p.s_n = wv(tn);
+    p.s_n2 = wv(tn + 1);
+    p.s_n3 = wv(tn + 2);
+    p.s_n4 = wv(tn + 3);
+    for (int k = 0; k < 4; ++k) p.s_more[k] = wv(tn + 4 + k);
+    p.rec = e.rec;
+    p.rec.col = tn;
+    p.nrun = e.march && ss.active && ss.t_end - ss.t >= ns ? ns : 0;
+    bp.img[slot] = p;
+}
+
+// State after the launches of a marching round (see launch_batch_advance_sel).
+__global__ __launch_bounds__(kAdvBlock) void k_batch_advance_sel(ShotState *state, const int32_t *order, int nact,
+                                                                 const StepParams *img, int sel, int run) {
+    const int a = blockIdx.x * kAdvBlock + threadIdx.x;
+    if (a >= nact) return;
+    const int slot = order[a];
+    ShotState &ss = state[slot];
+    const int nr = img[slot].nrun;
+    if (sel == 1) {
+        if (nr > 0) {
+            ss.t += nr;
+            ss.cur ^= 1;
+        }
+    } else if (nr == 0 && ss.active && ss.t < ss.t_end) {
+        ss.t += min<int64_t>(run, ss.t_end - ss.t);
+        ss.cur ^= 1;
+    }
+}
+
 // f(S(), integral_constant<int, Q>()) for the storage format and lattice.
 template <typename F>
 static auto by_config(int storage, int q, F &&f) {
@@ -99,6 +151,42 @@ hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp,
                                          : launch_stepn_batch_f64_q9(bp, ns, nwaves, s);
     if (storage == ST_F16 && q == 5) return launch_stepn_batch_f16_q5(bp, ns, nwaves, s);
     return hipErrorInvalidValue;
+}
+
+int64_t stepn_march_waves(int storage, int q, int kind, int32_t nx, int32_t ny) {
+    if (nx < 1 || ny < 1) return 0;
+    if (storage == ST_F32) return q == 5 ? march_waves_f32_q5(kind, nx, ny) : march_waves_f32_q9(kind, nx, ny);
+    if (storage == ST_F64) return q == 5 ? march_waves_f64_q5(kind, nx, ny) : march_waves_f64_q9(kind, nx, ny);
+    if (storage == ST_F16 && q == 5) return march_waves_f16_q5(kind, nx, ny);
+    return 0;
+}
+
+hipError_t launch_batch_march_prep(int q, const BatchParams &bp, int ns, hipStream_t s) {
+    if (bp.nact <= 0) return hipSuccess;
+    if (bp.img == nullptr || ns < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_march_prep, dim3((unsigned)((bp.nact + kAdvBlock - 1) / kAdvBlock)), dim3(kAdvBlock),
+                       0, s, bp, q, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_stepn_march_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s) {
+    if (nwaves <= 0 || bp.nact <= 0) return hipSuccess;
+    if (bp.img == nullptr || bp.mprefix == nullptr || (q != 5 && q != 9)) return hipErrorInvalidValue;
+    if (storage == ST_F32) return q == 5 ? launch_stepn_march_batch_f32_q5(bp, nwaves, s)
+                                         : launch_stepn_march_batch_f32_q9(bp, nwaves, s);
+    if (storage == ST_F64) return q == 5 ? launch_stepn_march_batch_f64_q5(bp, nwaves, s)
+                                         : launch_stepn_march_batch_f64_q9(bp, nwaves, s);
+    if (storage == ST_F16 && q == 5) return launch_stepn_march_batch_f16_q5(bp, nwaves, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_advance_sel(ShotState *state, const int32_t *order, int nact, const StepParams *img, int sel,
+                                    int run, hipStream_t s) {
+    if (nact <= 0) return hipSuccess;
+    if (img == nullptr || (sel != 1 && sel != 2)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_advance_sel, dim3((unsigned)((nact + kAdvBlock - 1) / kAdvBlock)), dim3(kAdvBlock), 0,
+                       s, state, order, nact, img, sel, run);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s) {

@@ -189,6 +189,7 @@ struct ShotEntry {
     double sponge_smax = 0.0;
     int32_t src_x = -1, src_y = -1;
     int32_t bx = 0;                          // step blocks per row
+    int32_t march = 0;                       // 1: the marching kernel takes the shape
 };
 
 // Dynamic state of a shot, advanced on the device.
@@ -208,6 +209,11 @@ struct BatchParams {
     int32_t nact = 0;
     int32_t max_run = 1;                     // blocked launch: steps per shot at most
     Collision coll;
+    // marching rounds: the first marching wave of each active shot, and the
+    // params image of each slot for the round (nrun > 0: the shot takes the
+    // marching launch; the round's other launches leave it alone)
+    const int64_t *mprefix = nullptr;        // [nact + 1]
+    StepParams *img = nullptr;               // [max_shots]; nullptr: no marching round
 };
 
 // Launchers (lb_kernels.hip).  All return the launch status.
@@ -234,6 +240,18 @@ hipError_t launch_batch_advance(ShotState *state, const int32_t *order, int nact
 int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny);   // kind: step_kind()
 hipError_t launch_stepn_batch(int storage, int q, int ns, const BatchParams &bp, int64_t nwaves, hipStream_t s);
 hipError_t launch_batch_advance_n(ShotState *state, const int32_t *order, int nact, int run, hipStream_t s);
+// Marching round of a batch (ns = stepn_march of the scheme): prep writes
+// bp.img for every active shot (nrun = ns for a shot whose shape the
+// marching kernel takes, with at least ns steps left; 0 otherwise), the
+// marching launch runs those over nwaves = sum of stepn_march_waves, and
+// advance_sel moves state: sel = 1 the marching shots by their nrun, sel = 2
+// the others by min(run, steps left).  The batched step launches of a round
+// (bp.img set) skip the marching shots.
+int64_t stepn_march_waves(int storage, int q, int kind, int32_t nx, int32_t ny);
+hipError_t launch_batch_march_prep(int q, const BatchParams &bp, int ns, hipStream_t s);
+hipError_t launch_stepn_march_batch(int storage, int q, const BatchParams &bp, int64_t nwaves, hipStream_t s);
+hipError_t launch_batch_advance_sel(ShotState *state, const int32_t *order, int nact, const StepParams *img, int sel,
+                                    int run, hipStream_t s);
 hipError_t launch_step(int storage, const StepParams &p, bool pull,
                        hipStream_t s);
 // ns pull steps in one launch of the temporally blocked ns-step kernel

@@ -545,6 +545,7 @@ __global__ __launch_bounds__(kStepBlock) void k_step_batch(BatchParams bp) {
         if (bp.prefix[mid] <= b) lo = mid; else hi = mid - 1;
     }
     const int slot = bp.order[lo];
+    if (bp.img != nullptr && bp.img[slot].nrun > 0) return;   // the round's marching launch takes it
     const ShotState ss = bp.state[slot];
     if (!ss.active || ss.t >= ss.t_end) return;
     const ShotEntry &e = bp.table[slot];

@@ -5,6 +5,7 @@ HIP kernels.  torch supplies device memory (the workspace, trace and field
 buffers) and the stream.  There is no CPU fallback: if the library is not
 built, importing the binding's entry points raises.
 """
+import collections
 import ctypes
 import os
 
@@ -32,7 +33,7 @@ EXPORTS = ("lb_default_desc", "lb_validate_desc", "lb_blocked_steps", "lb_worksp
            "lb_state_bytes", "lb_get_state", "lb_set_raw_state", "lb_sync",
            "lb_status_string", "lb_device_copy",
            "lb_batch_workspace_bytes", "lb_batch_create", "lb_shot_workspace_bytes",
-           "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times",
+           "lb_batch_add_shot", "lb_batch_remove_shot", "lb_batch_tick", "lb_batch_times", "lb_batch_completed",
            "lb_batch_sync", "lb_batch_destroy", "lb_misfit", "lb_adjoint", "lb_trace_misfit",
            "lb_trace_misfit_static")
 
@@ -128,6 +129,7 @@ def lib():
         "lb_batch_remove_shot": (ctypes.c_int, [vp, i32]),
         "lb_batch_tick": (ctypes.c_int, [vp, i64]),
         "lb_batch_times": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+        "lb_batch_completed": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
         "lb_batch_sync": (ctypes.c_int, [vp]),
         "lb_batch_destroy": (ctypes.c_int, [vp]),
         "lb_misfit": (ctypes.c_int, [vp, vp, i64, vp, vp]),
@@ -487,6 +489,7 @@ class Batch:
                                  ctypes.byref(h)), "lb_batch_create")
         self._h = h
         self.shots = {}
+        self._inflight = collections.deque()   # completion events of the ticks
 
     def shot_bytes(self, desc):
         return int(lib().lb_shot_workspace_bytes(self._h, ctypes.byref(desc)))
@@ -503,7 +506,6 @@ class Batch:
         w = np.ascontiguousarray(wavelet, dtype=np.float64)
         keep = []
         if isinstance(c2, torch.Tensor) and c2.is_cuda:
-            self.stream.wait_stream(torch.cuda.current_stream(self.device))
             c2 = c2.contiguous()
             keep.append(c2)
             cp, ct, dev = ctypes.c_void_p(c2.data_ptr()), (F64 if c2.dtype == torch.float64 else F32), 1
@@ -513,7 +515,10 @@ class Batch:
             cp, ct, dev = ctypes.c_void_p(arr.ctypes.data), F64, 0
         with torch.cuda.stream(self.stream):
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            traces = torch.zeros((max(desc.nrec, 1), desc.nsteps + 1), dtype=self.dtype, device=self.device)
+        traces = torch.zeros((max(desc.nrec, 1), desc.nsteps + 1), dtype=self.dtype, device=self.device)
+        # the library reads c2 and writes the traces on a stream of its own:
+        # both must be complete (the caller's stream, not the ticks, is waited on)
+        torch.cuda.current_stream(self.device).synchronize()
         slot = ctypes.c_int32(-1)
         _check(lib().lb_batch_add_shot(self._h, ctypes.byref(desc), ctypes.c_void_p(ws.data_ptr()),
                                        ctypes.c_size_t(nbytes), cp, ct, dev,
@@ -525,17 +530,44 @@ class Batch:
         return slot.value
 
     def remove(self, slot):
-        """Retire a shot; returns its trace tensor [nrec][nsteps + 1]."""
+        """Retire a shot; returns its trace tensor [nrec][nsteps + 1].  Work
+        queued afterwards on the caller's stream runs after the ticks
+        enqueued so far (no host wait)."""
         _check(lib().lb_batch_remove_shot(self._h, int(slot)), "lb_batch_remove_shot")
         info = self.shots.pop(int(slot))
+        self._torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return info["traces"]
 
     def tick(self, k):
         _check(lib().lb_batch_tick(self._h, int(k)), "lb_batch_tick")
+        ev = self._torch.cuda.Event()
+        ev.record(self.stream)
+        self._inflight.append(ev)
+
+    def in_flight(self):
+        """Ticks enqueued and not yet completed (no wait)."""
+        while self._inflight and self._inflight[0].query():
+            self._inflight.popleft()
+        return len(self._inflight)
+
+    def wait_oldest(self):
+        """Wait for the oldest tick in flight; False if there is none."""
+        if not self._inflight:
+            return False
+        self._inflight.popleft().synchronize()
+        return True
 
     def times(self):
+        """Times the slots reach once the enqueued ticks have run."""
         out = (ctypes.c_int64 * self.max_shots)()
         _check(lib().lb_batch_times(self._h, out), "lb_batch_times")
+        return np.frombuffer(out, dtype=np.int64).copy()
+
+    def completed(self):
+        """Times the slots have reached on the device (newest completed
+        tick; -1 where none has completed since admission).  No wait."""
+        out = (ctypes.c_int64 * self.max_shots)()
+        _check(lib().lb_batch_completed(self._h, out), "lb_batch_completed")
         return np.frombuffer(out, dtype=np.int64).copy()
 
     def sync(self):

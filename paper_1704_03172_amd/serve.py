@@ -10,9 +10,9 @@ replayed from a captured HIP graph.  A shot that reaches its last step stops
 updating inside the tick; once the tick has run, its traces are copied out
 and its slot and memory are freed.
 
-run_fifo() is the baseline on the same trace: one shot at a time, in arrival
-order, through the single-grid lb_step_n path (several steps per launch, one
-shot per launch).
+run_sequential() is the baseline on the same trace: one shot at a time,
+picked by the same admission policy, through the single-grid lb_step_n path
+(several steps per launch, one shot per launch).
 
 Latency of a request = completion - arrival = queue wait + service.
 """
@@ -44,20 +44,39 @@ def summarize(records, wall):
     }
 
 
+def _cost_s(req, rate):
+    """Estimated service time of a request alone on the GPU (seconds)."""
+    return req["n"] * req["n"] * req["nsteps"] / rate
+
+
+def _pick_order(queue, policy, now, rate, aging):
+    """Queue order for admission.  fifo: arrival order.  sjf: shortest
+    estimated service first, with aging: a request's key is s - aging * w
+    for service estimate s and queue wait w (seconds), so a large request
+    that has waited long enough goes before fresh small ones instead of
+    starving under overload."""
+    if policy == "fifo":
+        return sorted(queue, key=lambda r: r["arrival"])
+    return sorted(queue, key=lambda r: (_cost_s(r, rate) - aging * max(0.0, now - r["arrival"]), r["arrival"]))
+
+
 class ShotServer:
     """Continuous-batching server over the lb_batch executor.
 
-    Admission: requests are taken from the queue in arrival order
-    (policy="fifo") or shortest job first by n^2 * steps (policy="sjf") while
-    a slot is free, the memory footprint fits the budget and the active
+    Admission: requests are taken from the queue in the policy's order
+    (fifo: arrival; sjf: shortest estimated service first, aged) while a
+    slot is free, the memory footprint fits the budget and the active
     lattice nodes stay under node_cap (so that shots are not slowed down by
     too many batch mates: the step cost is proportional to the nodes).  Each
-    tick is sized to about tick_ms of GPU work at rate_lups.
+    tick is sized to about tick_ms of GPU work at rate_lups.  The host keeps
+    two ticks in flight: it enqueues the next tick while the GPU runs the
+    current one, admits new shots without waiting for the ticks, and retires
+    a shot once the tick that finished it has completed (lb_batch_completed).
     """
 
     def __init__(self, budget_bytes=64 << 30, max_slots=32, tick_steps=None,
                  precision="f32", use_graph=True, keep_traces=False, batch=None,
-                 policy="sjf", node_cap=4096 * 4096, tick_ms=20.0, rate_lups=2.0e11):
+                 policy="sjf", node_cap=4096 * 4096, tick_ms=20.0, rate_lups=4.0e11, aging=0.05):
         import torch
         from . import lbwave
         self.torch = torch
@@ -75,6 +94,7 @@ class ShotServer:
         self.node_cap = int(node_cap)
         self.tick_ms = float(tick_ms)
         self.rate = float(rate_lups)
+        self.aging = float(aging)
 
     def desc(self, req):
         return self.lbwave.shot_desc(req["n"], req["n"], req["src"], req["nsteps"], req["nrec"],
@@ -93,7 +113,7 @@ class ShotServer:
     def _tick_steps(self, nodes):
         if self.k_fixed is not None:
             return self.k_fixed
-        return int(max(10, min(500, self.tick_ms * 1e-3 * self.rate / max(nodes, 1))))
+        return int(max(16, min(512, self.tick_ms * 1e-3 * self.rate / max(nodes, 1))))
 
     def run(self, trace, progress=False):
         """Serve a list of requests (arrival in seconds from the start);
@@ -112,38 +132,45 @@ class ShotServer:
             tn = now()
             while pending and pending[0]["arrival"] <= tn:
                 queue.append(pending.popleft())
-            if self.policy == "sjf":
-                queue.sort(key=lambda r: (r["n"] * r["n"] * r["nsteps"], r["arrival"]))
-            while queue and len(active) < self.max_slots:
-                req = queue[0]
-                fp = self.footprint(req)
-                nn = req["n"] * req["n"]
-                if active and (used + fp > self.budget or nodes + nn > self.node_cap):
-                    break                      # wait for memory / GPU share
-                queue.pop(0)
-                slot = self._admit(req)
-                used += fp
-                nodes += nn
-                active[slot] = {"rid": req["rid"], "arrival": req["arrival"], "admit": now(),
-                                "n": req["n"], "nsteps": req["nsteps"], "bytes": fp, "nodes": nn}
+            if queue and len(active) < self.max_slots:
+                queue = _pick_order(queue, self.policy, tn, self.rate, self.aging)
+                while queue and len(active) < self.max_slots:
+                    req = queue[0]
+                    fp = self.footprint(req)
+                    nn = req["n"] * req["n"]
+                    if active and (used + fp > self.budget or nodes + nn > self.node_cap):
+                        break                      # wait for memory / GPU share
+                    queue.pop(0)
+                    slot = self._admit(req)
+                    used += fp
+                    nodes += nn
+                    active[slot] = {"rid": req["rid"], "arrival": req["arrival"], "admit": now(),
+                                    "n": req["n"], "nsteps": req["nsteps"], "bytes": fp, "nodes": nn}
+            # retire the shots whose last tick has run
+            if active:
+                comp = self.batch.completed()
+                for slot in list(active):
+                    rec = active[slot]
+                    if comp[slot] >= rec["nsteps"]:
+                        tr = self.batch.remove(slot)
+                        if self.keep:
+                            traces[rec["rid"]] = tr.cpu().numpy()
+                        rec["done"] = now()
+                        used -= rec["bytes"]
+                        nodes -= rec["nodes"]
+                        done.append(active.pop(slot))
+                        if progress and len(done) % 100 == 0:
+                            print("batched: %d done at %.1f s" % (len(done), now()), file=sys.stderr, flush=True)
             if not active:
-                if pending:
+                if pending and not queue:
                     time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - now())))
                 continue
-            self.batch.tick(self._tick_steps(nodes))
             times = self.batch.times()
-            for slot in list(active):
-                rec = active[slot]
-                if times[slot] >= rec["nsteps"]:
-                    tr = self.batch.remove(slot)
-                    if self.keep:
-                        traces[rec["rid"]] = tr.cpu().numpy()
-                    rec["done"] = now()
-                    used -= rec["bytes"]
-                    nodes -= rec["nodes"]
-                    done.append(active.pop(slot))
-                    if progress and len(done) % 100 == 0:
-                        print("batched: %d done at %.1f s" % (len(done), now()), file=sys.stderr, flush=True)
+            if self.batch.in_flight() < 2 and any(times[s] < r["nsteps"] for s, r in active.items()):
+                self.batch.tick(self._tick_steps(nodes))   # the next tick while one runs
+                continue
+            if not self.batch.wait_oldest():
+                time.sleep(0.0002)
         wall = max(r["done"] for r in done) - min(r["arrival"] for r in done) if done else 0.0
         self.traces = traces
         return done, summarize(done, wall)
@@ -152,18 +179,27 @@ class ShotServer:
         self.batch.close()
 
 
-def run_fifo(trace, precision="f32", keep_traces=False, progress=False):
-    """Baseline: one shot at a time in arrival order, through the
-    single-grid lb_step_n path (several steps per launch, no batching)."""
+def run_sequential(trace, policy="fifo", precision="f32", keep_traces=False, progress=False,
+                   rate_lups=4.0e11, aging=0.05):
+    """Baseline: one shot at a time through the single-grid lb_step_n path
+    (several steps per launch, no batching), the next shot chosen among the
+    arrived requests by the same policy as the batched server."""
     import torch
     from . import inputs, lbwave
     done = []
     traces = {}
+    pending = collections.deque(sorted(trace, key=lambda r: r["arrival"]))
+    queue = []
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
-    for req in sorted(trace, key=lambda r: r["arrival"]):
-        while now() < req["arrival"]:
-            time.sleep(min(0.01, req["arrival"] - now()))
+    while pending or queue:
+        while pending and pending[0]["arrival"] <= now():
+            queue.append(pending.popleft())
+        if not queue:
+            time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - now())))
+            continue
+        req = _pick_order(queue, policy, now(), rate_lups, aging)[0]
+        queue.remove(req)
         admit = now()
         n = req["n"]
         g = lbwave.Grid(n, n, lattice=5, collision="bgk", precision=precision, tau=0.5,
@@ -184,8 +220,15 @@ def run_fifo(trace, precision="f32", keep_traces=False, progress=False):
         g.close()
         del g, tr
     wall = max(r["done"] for r in done) - min(r["arrival"] for r in done) if done else 0.0
-    run_fifo.traces = traces
+    run_sequential.traces = traces
     return done, summarize(done, wall)
+
+
+def run_fifo(trace, precision="f32", keep_traces=False, progress=False):
+    """One shot at a time in arrival order (run_sequential with fifo)."""
+    out = run_sequential(trace, "fifo", precision, keep_traces, progress)
+    run_fifo.traces = run_sequential.traces
+    return out
 
 
 def main(argv=None):
@@ -198,7 +241,7 @@ def main(argv=None):
     ap.add_argument("--tick", type=int, default=None, help="fixed steps per tick (default: adaptive)")
     ap.add_argument("--policy", choices=("fifo", "sjf"), default="sjf")
     ap.add_argument("--node-cap", type=int, default=4096 * 4096)
-    ap.add_argument("--mode", choices=("batch", "fifo", "both"), default="both")
+    ap.add_argument("--mode", choices=("batch", "sequential", "both"), default="both")
     args = ap.parse_args(argv)
     import torch
     from . import inputs
@@ -213,9 +256,9 @@ def main(argv=None):
         _, out["batched"] = srv.run(trace, progress=True)
         srv.close()
         print("batched", json.dumps(out["batched"]), file=sys.stderr, flush=True)
-    if args.mode in ("fifo", "both"):
-        _, out["fifo"] = run_fifo(trace, progress=True)
-        print("fifo", json.dumps(out["fifo"]), file=sys.stderr, flush=True)
+    if args.mode in ("sequential", "both"):
+        _, out["one_shot_per_launch"] = run_sequential(trace, args.policy, progress=True)
+        print("one shot per launch", json.dumps(out["one_shot_per_launch"]), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

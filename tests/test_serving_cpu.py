@@ -77,6 +77,15 @@ class FakeBatch:
             out[s] = v
         return out
 
+    def completed(self):   # ticks complete at once
+        return self.times()
+
+    def in_flight(self):
+        return 0
+
+    def wait_oldest(self):
+        return False
+
     def remove(self, slot):
         import torch
         del self.t[slot]
@@ -134,3 +143,18 @@ def test_server_sjf_and_node_cap():
     assert fb.peak <= 9
     order = sorted(trace, key=lambda r: (r["n"] ** 2 * r["nsteps"], r["arrival"]))
     assert fb.adds[0] == order[0]["n"]          # all arrived at once: shortest first
+
+
+def test_sjf_aging_orders_long_waiters_first():
+    """With aging, a large request that has waited long goes before fresh
+    small ones; without waiting the order is shortest first."""
+    from paper_1704_03172_amd import serve
+    big = {"n": 4096, "nsteps": 4000, "arrival": 0.0}
+    small = {"n": 256, "nsteps": 1000, "arrival": 9.9}
+    rate = 4e11
+    s_big = 4096 * 4096 * 4000 / rate
+    assert serve._pick_order([big, small], "sjf", 0.0, rate, 0.05)[0] is small     # waits equal (none)
+    assert serve._pick_order([big, small], "sjf", 10.0, rate, 0.05)[0] is big       # waited 10 s
+    assert serve._pick_order([big, small], "sjf", 10.0, rate, 0.0)[0] is small      # no aging: starves
+    assert serve._pick_order([big, small], "fifo", 10.0, rate, 0.05)[0] is big
+    assert s_big - 0.05 * 10.0 < 0
