@@ -529,9 +529,9 @@ struct RareKernarg {
     __device__ KernargParams operator()() const { return rare_params(); }
 };
 struct RareGlobal {
-    const StepParams *img;
-    __device__ const StepParams *operator()() const {
-        const StepParams *q = img;
+    KernargParams img;
+    __device__ KernargParams operator()() const {
+        KernargParams q = img;
         asm volatile("" : "+s"(q));
         return q;
     }
@@ -858,11 +858,30 @@ __global__ __launch_bounds__(kT2Block) void k_stepn_march_batch(BatchParams bp, 
         if (bp.mprefix[mid] <= w) lo = mid; else hi = mid - 1;
     }
     const int slot = __builtin_amdgcn_readfirstlane(bp.order[lo]);
-    const StepParams *q = img + slot;
+    // the image through the constant address space: it is read-only while
+    // the launch runs, so its fields come in with scalar loads, into scalar
+    // registers (through a generic pointer they would be vector loads, and
+    // read again after every store of the walk)
+    const KernargParams q = (KernargParams)(img + slot);
     if (q->nrun != NS) return;
-    // a copy in registers: read through q, the fields would be read again
-    // after every store of the walk (the compiler cannot tell them apart)
-    const StepParams pl = *q;
+    StepParams pl;
+    pl.src = q->src;
+    pl.dst = q->dst;
+    pl.c2 = q->c2;
+    pl.nx = q->nx;
+    pl.ny = q->ny;
+    pl.pstride = q->pstride;
+    pl.q = q->q;
+    pl.coll.kind = q->coll.kind;
+    pl.coll.omega = q->coll.omega;
+    pl.coll.ratio = q->coll.ratio;
+    pl.coll.kw = q->coll.kw;
+    pl.coll.kax = q->coll.kax;
+    pl.coll.kdg = q->coll.kdg;
+    for (int i = 0; i < 9; ++i) pl.coll.srate[i] = q->coll.srate[i];
+    pl.sponge_width = q->sponge_width;
+    pl.src_y = q->src_y;
+    pl.rec.row_ptr = q->rec.row_ptr;
     march_wave<S, Q, KIND, NS>(pl, (int)(w - bp.mprefix[lo]), c2ring[wib], RareGlobal{q});
 }
 
