@@ -196,17 +196,19 @@ def adjoint_bench(torch, lbwave, inputs, n, nshots, nsteps, K=55, tape=True):
            "forward_ms_per_shot": round(t_fwd / nshots * 1e3, 2),
            "adjoint_ms_per_shot": round(t_adj / nshots * 1e3, 2),
            "misfit": float(phi.item()), "gradient_finite": finite}
+    # algorithmic bytes per node and step of the backward launches, three
+    # steps each (D2Q5): lambda in and out 40 B, c^2 4 B and the FP64
+    # gradient read and written 16 B once per launch, the rho of every step 4 B
+    adj_b = (40.0 + 4 + 16) / 3 + 4
     if tape:
-        # algorithmic bytes per node and step of the adjoint phase: the
-        # two-step adjoint launch (lambda in and out, c^2 and the FP64
-        # gradient read and written once per two steps, rho of both: 68 B)
-        out["adjoint_phase_GB_s"] = round(68 / 2.0 * N * nsteps / (t_adj / nshots) / 1e9, 1)
+        out["adjoint_phase_GB_s"] = round(adj_b * N * nsteps / (t_adj / nshots) / 1e9, 1)
     else:
         # plus the recompute (44 B per ns-step launch and the 4-byte rho
         # field of each step), through the rho-writing kernel
         ns_rec = lbwave.blocked_steps(nx=64, ny=64, precision="f32", steps_per_launch=4)
-        out["adjoint_phase_GB_s"] = round((44.0 / ns_rec + 4 + 68 / 2.0) * N * nsteps / (t_adj / nshots) / 1e9, 1)
+        out["adjoint_phase_GB_s"] = round((44.0 / ns_rec + 4 + adj_b) * N * nsteps / (t_adj / nshots) / 1e9, 1)
         out["recompute_steps_per_launch"] = ns_rec
+    out["backward_steps_per_launch"] = 3
     return out
 
 

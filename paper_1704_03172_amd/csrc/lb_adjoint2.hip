@@ -1,22 +1,27 @@
-// lb_adjoint2.hip -- two backward steps of the discrete adjoint per launch
-// (steps n and n-1 of the segment sweep in lb_adjoint), with the strip and
-// segment decomposition of the blocked forward kernel (lb_blocked.h): a
-// wavefront loads the rows of lambda(n+1) of its segment plus two halo rows
-// on each side, computes lambda(n) on the segment and one halo row on each
-// side (receiver residuals included, as the second step reads them), then
-// lambda(n-1) on its own rows, which it stores.  The FP64 gradient of the
-// owned nodes is read once, takes the terms of time n and then of time n-1
-// (the order of two one-step launches) and is written once.  Per node the
+// lb_adjoint2.hip -- several backward steps of the discrete adjoint per
+// launch (steps n, n-1, .., n-NS+1 of the sweep in lb_adjoint), with the strip
+// and segment decomposition of the blocked forward kernel (lb_blocked.h): a
+// wavefront loads the rows of lambda(n+1) of its segment plus NS halo rows on
+// each side, and stage s (1..NS) computes lambda(n-s+1) on the segment plus
+// NS - s halo rows on each side (receiver residuals included, as the later
+// stages read them); the last stage stores its own rows.  The FP64 gradient
+// of the owned nodes is read once, takes the terms of time n, then n-1, ...
+// (the order of one-step launches) and is written once.  Per node the
 // arithmetic is adjoint_node (lb_node.h), as in the one-step kernel, so the
-// gradient is the same bits; lambda crosses HBM once per two steps.
+// gradient is the same bits; lambda crosses HBM once per NS steps.
 #include "lb_blocked.h"
 
 namespace lbw {
 namespace {
 
-// Rows per segment (the two halo rows of each side are computed twice).
+// Most backward steps per launch, and rows per segment for NS steps (the
+// halo rows of each side are computed more than once).  D2Q5 at 2048^2
+// (FP32, per 3000-step shot): two steps 89.0 ms, three 71.7 ms (161 VGPRs,
+// three waves per SIMD), four 78.1 ms (193 VGPRs, two waves).
 template <typename T, int Q>
-constexpr int adj2_rows() { return Q == 5 ? 4 : 2; }
+constexpr int adjn_max() { return Q == 5 ? 3 : 2; }
+template <typename T, int Q, int NS>
+constexpr int adjn_rows() { return Q == 5 ? 4 : 2; }
 
 // mu_i(x) = lambda_i(n+1)(x + c_i): the transpose of the pull, from the row
 // below for c_y = +1 (D), above for c_y = -1 (U), and the lane to the right
@@ -45,10 +50,11 @@ __device__ inline void pull_back_row(const T (&U)[Q][V], const T (&C)[Q][V], con
     }
 }
 
-template <typename T, int Q, int KIND, bool VEC>
-__device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointParams &p, int wave) {
-    constexpr int V = Tb<T>::V, H = Tb<T>::H, OW = Tb<T>::OW, LY = adj2_rows<T, Q>(), K = LY + 4;
-    static_assert(H * V >= 2, "the strip halo must cover one column per step");
+template <typename T, int Q, int KIND, bool VEC, int NS>
+__device__ __attribute__((always_inline)) inline void adjn_wave(const AdjointParams &p, int wave) {
+    constexpr int V = Tb<T>::V, H = Tb<T>::H, OW = Tb<T>::OW, LY = adjn_rows<T, Q, NS>(), K = LY + 2 * NS;
+    static_assert(H * V >= NS, "the strip halo must cover one column per step");
+    static_assert(K - 2 <= 64, "the receiver row table of a segment is held one row per lane");
     const int nx = p.nx, ny = p.ny;
     const int nstrip = (nx + OW - 1) / OW;
     const int nseg = (ny + LY - 1) / LY;
@@ -71,15 +77,15 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
         dxw[j] = min(xw[j], nx - 1 - xw[j]);
     }
     const int xv = xw[0];
-    // receiver rows of walk rows 1 .. K-2 (grid rows y0-1 .. y0+LY): lane k
-    // holds the CSR range of walk row k + 1
+    // receiver rows of walk rows 1 .. K-2 (grid rows y0-NS+1 .. y0+LY+NS-2):
+    // lane k holds the CSR range of walk row k + 1
     int rb_l = 0, re_l = 0;
-    if (p.rec.row_ptr != nullptr && lane < (y1 - y0) + 2) {
-        const int w = wrapi(y0 - 1 + lane, ny);
+    if (p.rec.row_ptr != nullptr && lane < (y1 - y0) + 2 * NS - 2) {
+        const int w = wrapi(y0 - NS + 1 + lane, ny);
         rb_l = p.rec.row_ptr[w];
         re_l = p.rec.row_ptr[w + 1];
     }
-    int wr = wrapi(y0 - 2, ny);
+    int wr = wrapi(y0 - NS, ny);
     int wrow[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -88,38 +94,38 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
     }
     const T *ln = reinterpret_cast<const T *>(p.lam_next);
     const T *c2 = reinterpret_cast<const T *>(p.c2);
-    T L0[K][Q][V], L1[K][Q][V], C[K][V];
+    // L0: lambda(n+1); Ls: lambda(n-s+1) of stage s (the last stage stores)
+    T L0[K][Q][V], L1[K][Q][V], L2[K][Q][V], L3[K][Q][V], C[K][V];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t ro = (int64_t)wrow[k] * nx;
-        if (k < 4 || k >= K - 4) load_row2<VEC, 0, true, T, T, Q, V>(ln, p.pstride, ro, xv, xw, L0[k]);
+        if (k < 2 * NS || k >= K - 2 * NS) load_row2<VEC, 0, true, T, T, Q, V>(ln, p.pstride, ro, xv, xw, L0[k]);
         else load_row2<VEC, 0, false, T, T, Q, V>(ln, p.pstride, ro, xv, xw, L0[k]);
         if (k >= 1 && k <= K - 2) load_c2row<VEC, true, T, V>(c2, ro, xv, xw, C[k]);
     }
-    // rho of times n and n-1 and the FP64 gradient at the owned nodes
-    T R1[LY][V], R2[LY][V];
+    // rho of times n .. n-NS+1 and the FP64 gradient at the owned nodes
+    T R[NS][LY][V];
     double G[LY][V];
-    const T *rho1 = reinterpret_cast<const T *>(p.rho);
-    const T *rho2 = reinterpret_cast<const T *>(p.rho_prev);
 #pragma unroll
     for (int r = 0; r < LY; ++r) {
         const int gm = min(y0 + r, y1 - 1);   // rows past a short last segment repeat its last row (unused)
         const int64_t ro = (int64_t)gm * nx;
-        load_c2row<VEC, false, T, V>(rho1, ro, xv, xw, R1[r]);
-        load_c2row<VEC, false, T, V>(rho2, ro, xv, xw, R2[r]);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            load_c2row<VEC, false, T, V>(reinterpret_cast<const T *>(p.rho) - s * p.rho_back, ro, xv, xw, R[s][r]);
 #pragma unroll
         for (int j = 0; j < V; ++j) G[r][j] = own[j] ? p.grad[ro + xw[j]] : 0.0;
     }
 
-    // step st (1: time n, 2: time n-1) at walk row m (grid row y0 - 2 + m)
+    // step st (1: time n, 2: time n-1, ..) at walk row m (grid row y0 - NS + m)
     auto stage = [&](auto stc, auto mc) __attribute__((always_inline)) {
         constexpr int st = decltype(stc)::value;
         constexpr int m = decltype(mc)::value;
-        const int gm = y0 - 2 + m;
+        const int gm = y0 - NS + m;
         const bool owned_row = gm >= y0 && gm < y1;
-        if (st == 2 && !owned_row) return;
+        if (st == NS && !owned_row) return;
         const int wm = wrow[m];
-        auto &A = st == 1 ? L0 : L1;
+        auto &A = pick4<st - 1>(L0, L1, L2, L3);
         T mu[Q][V];
         pull_back_row<T, Q, V>(A[m - 1], A[m], A[m + 1], mu);
         // the sponge factor (1 - sigma) on mu: one wave-uniform test per row,
@@ -142,9 +148,9 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
             }
         }
         const int rb = __builtin_amdgcn_readlane(rb_l, m - 1), re = __builtin_amdgcn_readlane(re_l, m - 1);
-        const int64_t col = st == 1 ? p.rec.col : p.rec.col - 1;
-        const double sn = st == 1 ? p.s_n : p.s_prev;
-        const bool initial = st == 2 && p.initial_prev != 0;
+        const int64_t col = p.rec.col - (st - 1);
+        const double sn = p.s_back[st - 1];
+        const bool initial = p.initial_stage == st;
         T lo[Q][V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -152,22 +158,23 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
 #pragma unroll
             for (int i = 0; i < Q; ++i) muj[i] = mu[i][j];
             T rho = T(0);   // rho only feeds the gradient, kept at the owned rows
-            if constexpr (m >= 2 && m - 2 < LY) {
-                if (owned_row) rho = st == 1 ? R1[m - 2][j] : R2[m - 2][j];
+            if constexpr (m >= NS && m - NS < LY) {
+                if (owned_row) rho = R[st - 1][m - NS][j];
             }
             const double g = adjoint_node<T, Q, KIND>(p, muj, C[m][j], rho, xw[j], wm, min(dxw[j], dy), rb, re, col, sn,
                                                       initial, lam, false);
-            if constexpr (m >= 2 && m - 2 < LY) {
-                if (owned_row && own[j]) G[m - 2][j] += g;
+            if constexpr (m >= NS && m - NS < LY) {
+                if (owned_row && own[j]) G[m - NS][j] += g;
             }
 #pragma unroll
             for (int i = 0; i < Q; ++i) lo[i][j] = lam[i];
         }
-        if constexpr (st == 1) {
+        if constexpr (st < NS) {
+            auto &B = pick4<st>(L0, L1, L2, L3);
 #pragma unroll
             for (int i = 0; i < Q; ++i)
 #pragma unroll
-                for (int j = 0; j < V; ++j) L1[m][i][j] = lo[i][j];
+                for (int j = 0; j < V; ++j) B[m][i][j] = lo[i][j];
         } else {
             T *out = reinterpret_cast<T *>(p.lam);
             const int64_t ro = (int64_t)gm * nx;
@@ -190,12 +197,15 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
             }
         }
     };
-    static_for<2, K>([&](auto kc) __attribute__((always_inline)) {
+    // walk index k: stage st at row k - st, within the rows st .. K-1-st it
+    // computes (stage st - 1 produced row k - st + 1 at this same index)
+    static_for<2, K + NS - 1>([&](auto kc) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value;
-        if constexpr (k - 1 >= 1 && k - 1 <= K - 2)
-            stage(std::integral_constant<int, 1>{}, std::integral_constant<int, k - 1>{});
-        if constexpr (k - 2 >= 2 && k - 2 <= K - 3)
-            stage(std::integral_constant<int, 2>{}, std::integral_constant<int, k - 2>{});
+        static_for<1, NS + 1>([&](auto stc) __attribute__((always_inline)) {
+            constexpr int st = decltype(stc)::value;
+            if constexpr (k - st >= st && k - st <= K - 1 - st)
+                stage(stc, std::integral_constant<int, k - st>{});
+        });
     });
 #pragma unroll
     for (int r = 0; r < LY; ++r) {
@@ -207,34 +217,49 @@ __device__ __attribute__((always_inline)) inline void adj2_wave(const AdjointPar
     }
 }
 
-template <typename T, int Q, int KIND, bool VEC>
-__global__ __launch_bounds__(kT2Block) void k_adjoint2(AdjointParams p) {
+template <typename T, int Q, int KIND, bool VEC, int NS>
+__global__ __launch_bounds__(kT2Block) void k_adjointn(AdjointParams p) {
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    adj2_wave<T, Q, KIND, VEC>(p, xcd_block() * (kT2Block / 64) + wib);
+    adjn_wave<T, Q, KIND, VEC, NS>(p, xcd_block() * (kT2Block / 64) + wib);
 }
 
-template <typename T, int Q>
-hipError_t adjoint2_launch(const AdjointParams &p, hipStream_t s) {
-    constexpr int OW = Tb<T>::OW, LY = adj2_rows<T, Q>();
+template <typename T, int Q, int NS>
+hipError_t adjointn_launch(const AdjointParams &p, hipStream_t s) {
+    constexpr int OW = Tb<T>::OW, LY = adjn_rows<T, Q, NS>();
     const int64_t waves = (int64_t)((p.nx + OW - 1) / OW) * ((p.ny + LY - 1) / LY);
     const dim3 grid((unsigned)((waves + kT2Block / 64 - 1) / (kT2Block / 64)));
     const bool vec = p.nx % Tb<T>::V == 0, mrt = p.coll.kind == 1;
     if (mrt) {
-        if (vec) hipLaunchKernelGGL((k_adjoint2<T, Q, 1, true>), grid, dim3(kT2Block), 0, s, p);
-        else hipLaunchKernelGGL((k_adjoint2<T, Q, 1, false>), grid, dim3(kT2Block), 0, s, p);
+        if (vec) hipLaunchKernelGGL((k_adjointn<T, Q, 1, true, NS>), grid, dim3(kT2Block), 0, s, p);
+        else hipLaunchKernelGGL((k_adjointn<T, Q, 1, false, NS>), grid, dim3(kT2Block), 0, s, p);
     } else {
-        if (vec) hipLaunchKernelGGL((k_adjoint2<T, Q, 0, true>), grid, dim3(kT2Block), 0, s, p);
-        else hipLaunchKernelGGL((k_adjoint2<T, Q, 0, false>), grid, dim3(kT2Block), 0, s, p);
+        if (vec) hipLaunchKernelGGL((k_adjointn<T, Q, 0, true, NS>), grid, dim3(kT2Block), 0, s, p);
+        else hipLaunchKernelGGL((k_adjointn<T, Q, 0, false, NS>), grid, dim3(kT2Block), 0, s, p);
     }
     return hipGetLastError();
 }
 
+template <typename T, int Q>
+hipError_t adjointn_by_steps(const AdjointParams &p, int ns, hipStream_t s) {
+    if constexpr (adjn_max<T, Q>() >= 4) if (ns == 4) return adjointn_launch<T, Q, 4>(p, s);
+    if constexpr (adjn_max<T, Q>() >= 3) if (ns == 3) return adjointn_launch<T, Q, 3>(p, s);
+    if (ns == 2) return adjointn_launch<T, Q, 2>(p, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-hipError_t launch_adjoint2(int storage, const AdjointParams &p, hipStream_t s) {
-    if (p.nx < 1 || p.ny < 1 || p.terminal || p.rec.col < 1 || (p.q != 5 && p.q != 9)) return hipErrorInvalidValue;
-    if (storage == ST_F64) return p.q == 5 ? adjoint2_launch<double, 5>(p, s) : adjoint2_launch<double, 9>(p, s);
-    return p.q == 5 ? adjoint2_launch<float, 5>(p, s) : adjoint2_launch<float, 9>(p, s);
+int adjointn_max(int storage, int q) {
+    if (storage == ST_F64) return q == 5 ? adjn_max<double, 5>() : adjn_max<double, 9>();
+    return q == 5 ? adjn_max<float, 5>() : adjn_max<float, 9>();
+}
+
+hipError_t launch_adjointn(int storage, const AdjointParams &p, int ns, hipStream_t s) {
+    if (p.nx < 1 || p.ny < 1 || p.terminal || p.rec.col < ns - 1 || (p.q != 5 && p.q != 9) || ns < 2 ||
+        ns > adjointn_max(storage, p.q) || p.rho_back <= 0)
+        return hipErrorInvalidValue;
+    if (storage == ST_F64) return p.q == 5 ? adjointn_by_steps<double, 5>(p, ns, s) : adjointn_by_steps<double, 9>(p, ns, s);
+    return p.q == 5 ? adjointn_by_steps<float, 5>(p, ns, s) : adjointn_by_steps<float, 9>(p, ns, s);
 }
 
 }  // namespace lbw

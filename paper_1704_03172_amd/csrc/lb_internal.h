@@ -156,11 +156,12 @@ struct AdjointParams {
     Receivers rec;                     // tables + residual array in `traces`
     int32_t terminal = 0;              // 1: n = N (no step, lambda(N+1) = 0)
     int32_t initial = 0;               // 1: n = 0, add the initial-state term
-    // launch_adjoint2 (steps n = rec.col and n - 1): rho(n - 1), S(n - 1),
-    // and whether n - 1 = 0
-    const void *rho_prev = nullptr;
-    double s_prev = 0.0;
-    int32_t initial_prev = 0;
+    // launch_adjointn (steps n = rec.col, n - 1, .., n - ns + 1): the rho of
+    // time n - k at rho - k * rho_back elements, S(n - k) in s_back[k], and
+    // the stage (k + 1) whose time is 0 (0: none)
+    int64_t rho_back = 0;
+    double s_back[4] = {0, 0, 0, 0};
+    int32_t initial_stage = 0;
 };
 
 // Field extraction: one field of the state at the current time.
@@ -218,10 +219,12 @@ struct BatchParams {
 
 // Launchers (lb_kernels.hip).  All return the launch status.
 hipError_t launch_adjoint(int storage, const AdjointParams &p, hipStream_t s);
-// Two backward steps (n = p.rec.col and n - 1, 1 <= n < N) in one launch:
-// lambda(n+1) from p.lam_next, lambda(n-1) to p.lam, rho(n) in p.rho and
-// rho(n-1) in p.rho_prev; the gradient gets the terms of n, then of n - 1.
-hipError_t launch_adjoint2(int storage, const AdjointParams &p, hipStream_t s);
+// ns backward steps (n = p.rec.col down to n - ns + 1, ns - 1 <= n < N) in
+// one launch: lambda(n+1) from p.lam_next, lambda(n-ns+1) to p.lam, rho and
+// S of each time as in AdjointParams; the gradient gets the terms of n, then
+// of n - 1, ... (the order of one-step launches).  2 <= ns <= adjointn_max.
+hipError_t launch_adjointn(int storage, const AdjointParams &p, int ns, hipStream_t s);
+int adjointn_max(int storage, int q);
 // Trace misfit: res = traces - obs over columns 0 .. ncols-1 of nrec rows of
 // cap columns, and phi = 1/2 sum res^2 (FP64) through misfit_blocks(nrec,
 // ncols) block partials in `partial` (at most kMisfitMaxBlocks doubles), then

@@ -1100,12 +1100,15 @@ int lb_trace_misfit(const void *d_traces, const void *d_obs, void *d_res, int32_
 }
 
 // Backward steps n = b, b - 1, .., a of the adjoint, the forward rho of time
-// n at rho_base + (n - a) fields; two steps per launch where both lie in
-// [a, b] (and not at the terminal time nt).  cur_lam: the lambda buffer
-// holding lambda(b + 1), updated.
+// n at rho_base + (n - a) fields; up to adjointn_max steps per launch (capped
+// as the forward launches are, so steps_per_launch = 1 gives one step per
+// launch) where they lie in [a, b] and not at the terminal time nt.
+// cur_lam: the lambda buffer holding lambda(b + 1), updated.
 int adjoint_backward(lb_grid *h, lbw::AdjointParams &ap, char *rho_base, int64_t a, int64_t b, int64_t nt,
                      int &cur_lam) {
-    const size_t field = (size_t)h->main.nx * h->main.ny * h->tsize;
+    const int64_t n_nodes = (int64_t)h->main.nx * h->main.ny;
+    const size_t field = (size_t)n_nodes * h->tsize;
+    const int nmax = std::min(lbw::adjointn_max(h->storage, h->q), blocked_max(h));
     for (int64_t n = b; n >= a;) {
         ap.rho = rho_base + (size_t)(n - a) * field;
         ap.terminal = n == nt;
@@ -1114,16 +1117,16 @@ int adjoint_backward(lb_grid *h, lbw::AdjointParams &ap, char *rho_base, int64_t
         ap.lam = h->lam[1 - cur_lam];
         ap.s_n = source_at(h, n);
         ap.rec.col = n;
-        if (n != nt && n - 1 >= a && blocked_max(h) >= 2) {
-            ap.rho_prev = rho_base + (size_t)(n - 1 - a) * field;
-            ap.s_prev = source_at(h, n - 1);
-            ap.initial_prev = n - 1 == 0;
-            LB_TRY(h, lbw::launch_adjoint2(h->storage, ap, h->stream));
-            n -= 2;
+        const int ns = n == nt ? 1 : (int)std::min<int64_t>(nmax, n - a + 1);
+        if (ns >= 2) {
+            ap.rho_back = n_nodes;
+            for (int k = 0; k < 4; ++k) ap.s_back[k] = k < ns ? source_at(h, n - k) : 0.0;
+            ap.initial_stage = n < ns ? (int32_t)n + 1 : 0;   // the stage of time 0
+            LB_TRY(h, lbw::launch_adjointn(h->storage, ap, ns, h->stream));
         } else {
             LB_TRY(h, lbw::launch_adjoint(h->storage, ap, h->stream));
-            n -= 1;
         }
+        n -= ns;
         cur_lam = 1 - cur_lam;
     }
     return LB_OK;

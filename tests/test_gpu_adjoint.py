@@ -110,9 +110,12 @@ def test_rho_tape_gives_the_same_gradient(precision, kw):
     case = make_case(N=97, seed=6, **kw)
     a = gpu_gradient(case, precision, K=16)[1]
     b = gpu_gradient(case, precision, tape=True, check_state=True)[1]
-    c = gpu_gradient(case, precision, tape=True, steps_per_launch=1)[1]
     np.testing.assert_array_equal(a, b)
-    np.testing.assert_array_equal(a, c)
+    # backward launches of one, two and three steps (the default takes up to
+    # four for D2Q5, two for D2Q9)
+    for spl in (1, 2, 3):
+        c = gpu_gradient(case, precision, tape=True, steps_per_launch=spl)[1]
+        np.testing.assert_array_equal(a, c)
 
 
 def test_rho_tape_fp64_matches_oracle_adjoint():
