@@ -83,7 +83,6 @@ struct InterfaceParams {
                                        // ring states of fine times T+1 (mid), T+2 (end)
 };
 
-// One launch of the fused step (or of the collide-only variant).
 // Times of the launches of a captured graph that lb_step_n replays: the
 // launches carry times relative to the first time t0 of the replayed chunk,
 // and t0 and the chunk's source amplitudes s[k] = S(t0 + 1 + k) sit here, in
@@ -95,6 +94,7 @@ struct GraphTab {
     double s[kGraphMaxSteps + 8] = {};   // (zeros past the chunk: a launch reads four)
 };
 
+// One launch of the fused step (or of the collide-only variant).
 struct StepParams {
     const void *src = nullptr;         // populations read
     void *dst = nullptr;               // populations written
