@@ -178,33 +178,92 @@ __device__ inline void ring_interp(const InterfaceParams &p, int i, int j, typen
     }
 }
 
-// The outer-ring states of the two fine steps of one coarse step T -> T+2,
-// one thread per fine ring node: R_{1/2} of the coarse state interpolated to
-// the node, at T+1 (mean of the ring-line snapshot of T and the coarse state
-// of T+2) and at T+2, each followed by the fine collision.
-template <typename S, int KIND>
-__device__ inline void prolong_pair_node(const InterfaceParams &p, int r) {
+// Blocks of NT fine outer-ring nodes: each side of the ring (top, bottom,
+// left, right, in the ring's order) in runs of NT, so that no block spans a
+// corner.
+template <int NT>
+__host__ __device__ inline int ring_tile_blocks(const PatchGeom &g) {
+    return 2 * ((g.nxf + NT - 1) / NT) + 2 * ((g.nyf - 2 + NT - 1) / NT);
+}
+
+// The outer-ring states of the two fine steps of one coarse step T -> T+2:
+// R_{1/2} of the coarse state interpolated to each fine ring node, at T+1
+// (mean of the ring-line snapshot of T and the coarse state of T+2) and at
+// T+2, each followed by the fine collision.  Block b (of ring_tile_blocks)
+// takes NT consecutive nodes of one side.  Their stencils (the copy of a
+// coincident coarse node, or the cubic (-1, 9, 9, -1)/16 along the side; see
+// ring_stencil) cover at most NT/2 + 5 consecutive nodes of that side's
+// ring line, which the block first pulls from the coarse state and reads
+// from the snapshot into an LDS tile, once each instead of once per stencil
+// that reaches them (up to three).  The stencil arithmetic then reads the
+// tile.  All NT threads of the block must call this (it synchronises).
+template <typename S, int KIND, int NT>
+__device__ inline void prolong_pair_tile(const InterfaceParams &p, int b) {
     using T = typename Tr<S>::T;
+    constexpr int NE = NT / 2 + 5;
+    __shared__ T tn[5][NE], ts[5][NE];
     const PatchGeom &g = p.g;
-    if (r >= g.nring) return;
-    int i, j;
-    if (r < g.nxf) { i = r; j = 0; }
-    else if (r < 2 * g.nxf) { i = r - g.nxf; j = g.nyf - 1; }
-    else if (r < 2 * g.nxf + g.nyf - 2) { i = 0; j = 1 + r - 2 * g.nxf; }
-    else { i = g.nxf - 1; j = 1 + r - 2 * g.nxf - (g.nyf - 2); }
-    int nodes_x[4], nodes_y[4], sidx[4];
-    T wt[4];
-    ring_stencil<T>(g, i, j, nodes_x, nodes_y, sidx, wt);
-    // every load of the node up front (one round of memory latency); the
-    // weight-0 entries of a coincident node repeat a valid node
-    T gn[4][5], gs[4][5];
+    const int bh = (g.nxf + NT - 1) / NT, bv = (g.nyf - 2 + NT - 1) / NT;
+    int side, c;
+    if (b < bh) { side = 0; c = b; }
+    else if (b < 2 * bh) { side = 1; c = b - bh; }
+    else if (b < 2 * bh + bv) { side = 2; c = b - 2 * bh; }
+    else if (b < 2 * bh + 2 * bv) { side = 3; c = b - 2 * bh - bv; }
+    else return;   // the whole block
+    const bool horiz = side < 2;
+    const int nh = g.W + 3, nv = g.H + 3;
+    const int nline = horiz ? nh : nv;   // ring-line nodes of the side
+    const int lbase = side == 0 ? 0 : side == 1 ? nh : side == 2 ? 2 * nh : 2 * nh + nv;
+    // along-side fine index u of thread 0 (i on the top and bottom rows, j
+    // on the left and right columns); line node e is coarse node
+    // (X0 - 1 + e, row) or (column, Y0 - 1 + e)
+    const int u0 = (horiz ? 0 : 1) + c * NT;
+    const int e_lo = u0 > 0 ? (u0 - 1) / 2 : 0;
+    const int crow = g.Y0 + (side == 1 ? g.H : 0), ccol = g.X0 + (side == 3 ? g.W : 0);
     const T *snap = reinterpret_cast<const T *>(p.snap);
+    for (int k = threadIdx.x; k < NE; k += NT) {
+        const int e = e_lo + k;
+        if (e < nline) {
+            T gn[5];
+            pre_at<S, T>(p.coarse, horiz ? g.X0 - 1 + e : ccol, horiz ? crow : g.Y0 - 1 + e, gn);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        pre_at<S, T>(p.coarse, nodes_x[s], nodes_y[s], gn[s]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) gs[s][q] = snap[q * g.nsnap + sidx[s]];
+            for (int q = 0; q < 5; ++q) {
+                tn[q][k] = gn[q];
+                ts[q][k] = snap[q * g.nsnap + lbase + e];
+            }
+        }
     }
+    __syncthreads();
+    const int u = u0 + (int)threadIdx.x;
+    if (c * NT + (int)threadIdx.x >= (horiz ? g.nxf : g.nyf - 2)) return;
+    const int i = horiz ? u : (side == 2 ? 0 : g.nxf - 1);
+    const int j = horiz ? (side == 0 ? 0 : g.nyf - 1) : u;
+    const int r = (side == 0 ? 0 : side == 1 ? g.nxf : side == 2 ? 2 * g.nxf : 2 * g.nxf + g.nyf - 2) + c * NT +
+                  (int)threadIdx.x;
+    // the stencil of ring_stencil, as tile entries; the weight-0 entries of
+    // a coincident node repeat it
+    int ek[4];
+    T wt[4];
+    if ((u & 1) == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            ek[s] = u / 2 + 1 - e_lo;
+            wt[s] = s == 1 ? T(1) : T(0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ek[s] = (u - 1) / 2 + s - e_lo;
+        wt[0] = wt[3] = T(-1) / T(16);
+        wt[1] = wt[2] = T(9) / T(16);
+    }
+    T gn[4][5], gs[4][5];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            gn[s][q] = tn[q][ek[s]];
+            gs[s][q] = ts[q][ek[s]];
+        }
     T mid[5], end[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) mid[q] = end[q] = T(0);
@@ -354,7 +413,7 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepParams
         // runs them as a launch of their own, whose registers would lower
         // this kernel's occupancy)
         if ((int)blockIdx.y < p.pre_rows) {
-            prolong_pair_node<S, KIND>(p.iface, ((int)blockIdx.y * gridDim.x + blockIdx.x) * kStepBlock + threadIdx.x);
+            prolong_pair_tile<S, KIND, kStepBlock>(p.iface, (int)blockIdx.y * gridDim.x + blockIdx.x);
             return;
         }
     }
@@ -716,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(InterfaceParams p) {
 
 template <typename S, int KIND>
 __global__ __launch_bounds__(kBlock) void k_prolong_pair(InterfaceParams p) {
-    prolong_pair_node<S, KIND>(p, blockIdx.x * kBlock + threadIdx.x);
+    prolong_pair_tile<S, KIND, kBlock>(p, blockIdx.x);
 }
 
 // ---- dispatch helpers ----------------------------------------------------------
@@ -733,13 +792,12 @@ hipError_t step_dispatch(const StepParams &p0, bool pull, hipStream_t s) {
     StepParams p = p0;
     p.pre_rows = 0;
     if (p0.prolong_on) {
-        const int64_t per_row = (int64_t)grid.x * kStepBlock;
-        const int rows = (int)((p0.iface.g.nring + per_row - 1) / per_row);
+        const int rows = (int)((ring_tile_blocks<kStepBlock>(p0.iface.g) + grid.x - 1) / grid.x);
         if (!kIsF64<S> && (int64_t)p0.ny + rows <= 65535) {
             p.pre_rows = rows;
             grid.y += (unsigned)rows;
         } else {   // a launch of its own first
-            dim3 pg(blocks_for(p0.iface.g.nring));
+            dim3 pg((unsigned)ring_tile_blocks<kBlock>(p0.iface.g));
             if (kind == 1) hipLaunchKernelGGL((k_prolong_pair<S, 1>), pg, dim3(kBlock), 0, s, p0.iface);
             else if (kind == 2) hipLaunchKernelGGL((k_prolong_pair<S, 2>), pg, dim3(kBlock), 0, s, p0.iface);
             else hipLaunchKernelGGL((k_prolong_pair<S, 0>), pg, dim3(kBlock), 0, s, p0.iface);
@@ -936,7 +994,14 @@ hipError_t launch_field(int storage, const FieldParams &p, hipStream_t s) {
 
 hipError_t launch_prolong(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong, p.g.nring) }
 
-hipError_t launch_prolong_pair(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_prolong_pair, p.g.nring) }
+hipError_t launch_prolong_pair(int storage, const InterfaceParams &p, hipStream_t s) {
+    dim3 grid((unsigned)ring_tile_blocks<kBlock>(p.g));   // one side's nodes per block
+    const int kind = step_kind(p.coll);
+    if (storage == ST_F32) LBW_IFACE_KIND(k_prolong_pair, float);
+    else if (storage == ST_F64) LBW_IFACE_KIND(k_prolong_pair, double);
+    else LBW_IFACE_KIND(k_prolong_pair, _Float16);
+    return hipGetLastError();
+}
 hipError_t launch_restrict(int storage, const InterfaceParams &p, hipStream_t s) { LBW_IFACE(k_restrict, p.g.ninner) }
 
 }  // namespace lbw
