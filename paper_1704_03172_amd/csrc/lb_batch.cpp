@@ -20,7 +20,7 @@
 
 namespace {
 
-constexpr int64_t kGraphSteps = 16;      // steps per captured graph
+constexpr int64_t kGraphSteps = 16;      // steps per captured graph (at least; see graph_steps)
 constexpr size_t kStageBytes = 4 << 20;  // pinned staging of the uploads
 constexpr int kTickEvents = 64;          // ticks whose completion can be tracked at once
 
@@ -302,10 +302,15 @@ void drop_graph(lb_batch *b) {
     b->graph = nullptr;
 }
 
+// Steps per captured graph: kGraphSteps rounded up to whole marching rounds.
+int64_t graph_steps(const lb_batch *b) {
+    return b->nsm > 1 ? (kGraphSteps + b->nsm - 1) / b->nsm * b->nsm : kGraphSteps;
+}
+
 int capture(lb_batch *b, const std::vector<char> &need) {
     drop_graph(b);
     BT_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_steps(b, kGraphSteps, need);
+    int rc = enqueue_steps(b, graph_steps(b), need);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc) {
@@ -583,17 +588,18 @@ int lb_batch_tick(lb_batch *b, int64_t k) {
         if ((rc = enqueue_steps(b, k, round_needs(b, k)))) return rc;
         advance_host(b, k);
     } else {
-        // graphs of kGraphSteps steps, captured again when the set of active
-        // shots changes or a round's short-shot launches come or go, and
-        // replayed; the remainder of k runs as direct launches
-        for (int64_t i = 0; i < k / kGraphSteps; ++i) {
-            const std::vector<char> need = round_needs(b, kGraphSteps);
+        // graphs of graph_steps() steps, captured again when the set of
+        // active shots changes or a round's short-shot launches come or go,
+        // and replayed; the remainder of k runs as direct launches
+        const int64_t gs = graph_steps(b);
+        for (int64_t i = 0; i < k / gs; ++i) {
+            const std::vector<char> need = round_needs(b, gs);
             if (b->dirty || !b->exec || need != b->graph_sig)
                 if ((rc = capture(b, need))) return rc;
             BT_TRY(b, hipGraphLaunch(b->exec, b->stream));
-            advance_host(b, kGraphSteps);
+            advance_host(b, gs);
         }
-        const int64_t r = k % kGraphSteps;
+        const int64_t r = k % gs;
         if ((rc = enqueue_steps(b, r, round_needs(b, r)))) return rc;
         advance_host(b, r);
     }

@@ -484,14 +484,17 @@ template <typename S, int NS> struct MTb {
     static constexpr int OW = (64 - 2 * H) * V;
 };
 // Segment height, prefetch distance and ring length, measured at 4096^2 on
-// MI355X (us per step, D2Q5 FP32): eight steps per launch with LY = 24,
-// PD = 3 for BGK at tau = 1/2 (33.5; LY 18 / 30 / 36 / 42: 35.1 / 35.9 / 35.0
-// / 37.7, more tail waves or more halo; PD 2 with U = 5: 33.6 at 176
-// VGPRs, still two waves per SIMD) and six with PD = 2 for MRT, whose larger
-// collision makes the third wave per SIMD worth more than two steps
-// (40.2 at 152 VGPRs; eight steps 45.1, seven 44.0).
+// MI355X (us per step, D2Q5 FP32).  BGK at tau = 1/2: seven steps per launch
+// with LY = 20, PD = 2, U = 5 (30.66 at 166 VGPRs: three waves per SIMD;
+// LY 25 30.66, LY 15 / 30 / 35: 31.2 / 33.2 / 34.0; U = 6 with LY 18 / 24:
+// 30.7 / 31.8; PD 1 with U = 4: 32.7).  The third wave per SIMD is what pays:
+// eight steps need 176-187 VGPRs, two waves (33.5 at its best: LY 24, PD 3,
+// U 6), six steps run at 36.6 and one column per lane (V = 1, four waves)
+// at 35.1-35.9.  MRT: six steps with PD = 2, U = 6, LY = 24, whose larger
+// collision makes the third wave per SIMD worth more than two steps (40.2
+// at 152 VGPRs; eight steps 45.1, seven 44.0).
 template <typename S, int Q, int KIND, int NS> struct March {
-    static constexpr int LY = 24, PD = NS <= 6 ? 2 : 3, U = 6;
+    static constexpr int LY = KIND == 1 ? 24 : 20, PD = 2, U = KIND == 1 ? 6 : 5;
     static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
 };
 
@@ -917,10 +920,10 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
 // marching 24-row segments ran at the speed of the 6-row kernel (45.0
 // against 44.4 us per step; both are held by the memory access pattern, not
 // by their arithmetic), so the marching kernel only takes the step counts
-// that the short segments cannot afford: eight for BGK (33.5 us per step),
+// that the short segments cannot afford: seven for BGK (30.7 us per step),
 // six for MRT (see March).
 template <typename S, int Q, int KIND>
-constexpr int march_steps() { return std::is_same_v<S, float> && Q == 5 ? (KIND == 1 ? 6 : 8) : 0; }
+constexpr int march_steps() { return std::is_same_v<S, float> && Q == 5 ? (KIND == 1 ? 6 : 7) : 0; }
 
 // The marching kernel's step count for a grid, 0 if it does not take it.
 template <typename S, int Q>

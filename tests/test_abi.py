@@ -92,19 +92,21 @@ def test_validate(lw, kw, code):
     assert (nb > 0) == (code == 0)
 
 
-@pytest.mark.parametrize("q,coll,prec,ns,nsm", [
-    (5, "bgk", "f32", 4, 8), (5, "mrt", "f32", 4, 6), (5, "bgk", "f64", 4, 4), (5, "mrt", "f16s", 3, 3),
-    (9, "bgk", "f32", 3, 3), (9, "mrt", "f32", 3, 3), (9, "mrt", "f64", 4, 4), (9, "bgk", "f16s", 1, 1)])
-def test_blocked_steps(lw, q, coll, prec, ns, nsm):
+@pytest.mark.parametrize("q,coll,prec,ns,nsm,ly", [
+    (5, "bgk", "f32", 4, 7, 20), (5, "mrt", "f32", 4, 6, 24), (5, "bgk", "f64", 4, 4, 0), (5, "mrt", "f16s", 3, 3, 0),
+    (9, "bgk", "f32", 3, 3, 0), (9, "mrt", "f32", 3, 3, 0), (9, "mrt", "f64", 4, 4, 0), (9, "bgk", "f16s", 1, 1, 0)])
+def test_blocked_steps(lw, q, coll, prec, ns, nsm, ly):
     """Steps per launch of lb_step_n for each configuration: ns with the
-    short-segment kernel, nsm where the marching kernel takes the grid
-    (D2Q5 FP32, ny >= 24 + 2 nsm: eight steps for BGK, six for MRT); the
-    cap of steps_per_launch (rounded
+    short-segment kernel, nsm where the marching kernel (segments of ly
+    rows) takes the grid (D2Q5 FP32, ny >= ly + 2 nsm: seven steps for BGK,
+    six for MRT); the cap of steps_per_launch (rounded
     down to a count a kernel takes), one step with a patch, and the
     validation errors."""
     kw = dict(nx=64, ny=64, lattice=q, collision=coll, precision=prec, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])
     assert lw.blocked_steps(**kw) == nsm
-    assert lw.blocked_steps(**dict(kw, ny=23 + 2 * nsm)) == ns   # too short for the marching kernel
+    if ly:
+        assert lw.blocked_steps(**dict(kw, ny=ly + 2 * nsm)) == nsm
+        assert lw.blocked_steps(**dict(kw, ny=ly + 2 * nsm - 1)) == ns   # too short for the marching kernel
     assert lw.blocked_steps(**dict(kw, nx=63)) == ns        # odd width: no vector accesses
     for cap in range(1, 9):
         want = nsm if cap >= nsm else min(cap, ns)
