@@ -108,19 +108,19 @@ typedef struct lb_grid lb_grid;
  *                  two adjoint population sets).  0: no checkpoints.
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
  *   steps_per_launch  0 (default): lb_step_n advances several time steps
- *                  per kernel launch (temporal blocking: for D2Q5 with
- *                  FP32 populations seven (BGK) or six (MRT) on grids with
- *                  nx even and ny >= 34 (BGK) or 36 (MRT), four for D2Q5
- *                  otherwise and for D2Q9 with FP64
- *                  populations, three for D2Q9 with FP32 populations, three
- *                  for D2Q5 and one for D2Q9 with FP16 storage;
+ *                  per kernel launch (temporal blocking: with FP32
+ *                  populations on grids with nx even, seven for D2Q5 when
+ *                  ny >= 34, six for D2Q9 BGK when ny >= 32 and five for
+ *                  D2Q9 MRT when ny >= 30; otherwise four for D2Q5 and
+ *                  three for D2Q9; four with FP64 populations; three for
+ *                  D2Q5 and one for D2Q9 with FP16 storage;
  *                  lb_blocked_steps reports the count) wherever it can (no
  *                  patch, no sum-rho recording, no checkpoint falling inside
  *                  a launch; the last launch of each call takes one step),
  *                  which divides the HBM traffic per step accordingly; the
  *                  results equal those of one step per launch bit for bit.
  *                  1 .. 8: at most that many steps per launch (a launch
- *                  takes 1 .. 4 steps, or the six or seven offered).
+ *                  takes 1 .. 4 steps, or the marching count offered).
  *   nbatch         independent shots sharing the grid shape (must be 1).
  *   rho_tape       1: lb_step_n also keeps the pre-collision rho of every
  *                  time 0 .. trace_capacity - 1 of the run since lb_set_state

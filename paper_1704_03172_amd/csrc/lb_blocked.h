@@ -484,17 +484,19 @@ template <typename S, int NS> struct MTb {
     static constexpr int OW = (64 - 2 * H) * V;
 };
 // Segment height, prefetch distance and ring length, measured at 4096^2 on
-// MI355X (us per step, D2Q5 FP32).  BGK at tau = 1/2: seven steps per launch
+// MI355X (us per step, FP32).  D2Q5 BGK at tau = 1/2: seven steps per launch
 // with LY = 20, PD = 2, U = 5 (30.66 at 166 VGPRs: three waves per SIMD;
 // LY 25 30.66, LY 15 / 30 / 35: 31.2 / 33.2 / 34.0; U = 6 with LY 18 / 24:
 // 30.7 / 31.8; PD 1 with U = 4: 32.7).  The third wave per SIMD is what pays:
 // eight steps need 176-187 VGPRs, two waves (33.5 at its best: LY 24, PD 3,
 // U 6), six steps run at 36.6 and one column per lane (V = 1, four waves)
-// at 35.1-35.9.  MRT: six steps with PD = 2, U = 6, LY = 24, whose larger
-// collision makes the third wave per SIMD worth more than two steps (40.2
-// at 152 VGPRs; eight steps 45.1, seven 44.0).
+// at 35.1-35.9.  D2Q5 MRT: seven steps 37.2 (166 VGPRs), six 39.1 (152;
+// 40.5 with U = 6, LY = 24), five 43.5.  D2Q9 BGK at tau = 1/2: six steps
+// 63.1 (254 VGPRs, two waves), five 70.2-72.8, four 79.5-80.9 (the
+// short-segment kernel, three steps: 102.2).  D2Q9 MRT: five steps 86.4
+// (230 VGPRs), four 88.0-89.8, six 87.8 (three steps: 117.0).
 template <typename S, int Q, int KIND, int NS> struct March {
-    static constexpr int LY = KIND == 1 ? 24 : 20, PD = 2, U = KIND == 1 ? 6 : 5;
+    static constexpr int LY = 20, PD = 2, U = 5;
     static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
 };
 
@@ -920,10 +922,10 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
 // marching 24-row segments ran at the speed of the 6-row kernel (45.0
 // against 44.4 us per step; both are held by the memory access pattern, not
 // by their arithmetic), so the marching kernel only takes the step counts
-// that the short segments cannot afford: seven for BGK (30.7 us per step),
-// six for MRT (see March).
+// that the short segments cannot afford: seven for D2Q5 (30.7 us per step
+// for BGK), six for D2Q9 BGK and five for D2Q9 MRT (see March).
 template <typename S, int Q, int KIND>
-constexpr int march_steps() { return std::is_same_v<S, float> && Q == 5 ? (KIND == 1 ? 6 : 7) : 0; }
+constexpr int march_steps() { return std::is_same_v<S, float> ? (Q == 5 ? 7 : KIND == 1 ? 5 : 6) : 0; }
 
 // The marching kernel's step count for a grid, 0 if it does not take it.
 template <typename S, int Q>

@@ -93,13 +93,13 @@ def test_validate(lw, kw, code):
 
 
 @pytest.mark.parametrize("q,coll,prec,ns,nsm,ly", [
-    (5, "bgk", "f32", 4, 7, 20), (5, "mrt", "f32", 4, 6, 24), (5, "bgk", "f64", 4, 4, 0), (5, "mrt", "f16s", 3, 3, 0),
-    (9, "bgk", "f32", 3, 3, 0), (9, "mrt", "f32", 3, 3, 0), (9, "mrt", "f64", 4, 4, 0), (9, "bgk", "f16s", 1, 1, 0)])
+    (5, "bgk", "f32", 4, 7, 20), (5, "mrt", "f32", 4, 7, 20), (5, "bgk", "f64", 4, 4, 0), (5, "mrt", "f16s", 3, 3, 0),
+    (9, "bgk", "f32", 3, 6, 20), (9, "mrt", "f32", 3, 5, 20), (9, "mrt", "f64", 4, 4, 0), (9, "bgk", "f16s", 1, 1, 0)])
 def test_blocked_steps(lw, q, coll, prec, ns, nsm, ly):
     """Steps per launch of lb_step_n for each configuration: ns with the
     short-segment kernel, nsm where the marching kernel (segments of ly
-    rows) takes the grid (D2Q5 FP32, ny >= ly + 2 nsm: seven steps for BGK,
-    six for MRT); the cap of steps_per_launch (rounded
+    rows) takes the grid (FP32, ny >= ly + 2 nsm: seven steps for D2Q5, six
+    for D2Q9 BGK, five for D2Q9 MRT); the cap of steps_per_launch (rounded
     down to a count a kernel takes), one step with a patch, and the
     validation errors."""
     kw = dict(nx=64, ny=64, lattice=q, collision=coll, precision=prec, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])

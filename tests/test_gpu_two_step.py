@@ -191,8 +191,9 @@ def test_two_step_vs_oracle_pulse_f64():
 
 def marching_receivers(nx, ny):
     """Receivers on the strip edges of the marching kernel (owned widths 112
-    and 116 columns for seven and six steps), on its segment edges (20 rows
-    for BGK, 24 for MRT), on the periodic seam and in the sponge."""
+    and 116 columns for seven and for five or six steps), on its 20-row
+    segment edges (and 24-row ones), on the periodic seam and in the
+    sponge."""
     xs = {0, 1, nx - 1, nx - 2}
     for w in (112, 116):
         for k in range(1, nx // w + 1):
@@ -208,13 +209,14 @@ def marching_receivers(nx, ny):
 
 
 @pytest.mark.parametrize("q,collision,s", [(5, "bgk", None), (5, "bgk", 0.8), (5, "mrt", [1, 1, 1, 1.6, 1.3]),
-                                           (5, "mrt", [1, 1, 1, 2, 2])])
-@pytest.mark.parametrize("nx,ny", [(500, 40), (500, 39), (462, 36), (462, 35), (500, 34), (462, 33), (230, 41),
-                                   (346, 71), (226, 97), (448, 48), (114, 64), (344, 61)])
+                                           (5, "mrt", [1, 1, 1, 2, 2]), (9, "bgk", None), (9, "bgk", 0.8),
+                                           (9, "mrt", [1, 1, 1, 2, 2, 2, 1, 1, 2])])
+@pytest.mark.parametrize("nx,ny", [(500, 40), (462, 36), (500, 34), (462, 33), (500, 32), (462, 31), (500, 30),
+                                   (462, 29), (230, 41), (346, 71), (226, 97), (448, 48), (114, 64), (344, 61)])
 def test_marching_kernel_shapes(q, collision, s, nx, ny):
-    """D2Q5 FP32 grids that take the marching kernel (seven steps per launch
-    for BGK when ny >= 34, on 20-row segments; six for MRT when ny >= 36, on
-    24-row segments) and
+    """FP32 grids that take the marching kernel (20-row segments; seven steps
+    per launch for D2Q5 when ny >= 34, six for D2Q9 BGK when ny >= 32, five
+    for D2Q9 MRT when ny >= 30) and
     grids just too short for it: heights around the thresholds, ragged last
     segments, widths that leave a partial last strip, step counts of every
     remainder, receivers and the source on strip and segment edges; bitwise
