@@ -112,8 +112,9 @@ typedef struct lb_grid lb_grid;
  *                  populations on grids with nx even, seven for D2Q5 when
  *                  ny >= 34, six for D2Q9 BGK when ny >= 32 and five for
  *                  D2Q9 MRT when ny >= 30; otherwise four for D2Q5 and
- *                  three for D2Q9; four with FP64 populations; three for
- *                  D2Q5 and one for D2Q9 with FP16 storage;
+ *                  three for D2Q9; four with FP64 populations; with FP16
+ *                  storage five for D2Q5 when nx is a multiple of 4 and
+ *                  ny >= 30, otherwise three, and one for D2Q9;
  *                  lb_blocked_steps reports the count) wherever it can (no
  *                  patch, no sum-rho recording, no checkpoint falling inside
  *                  a launch; the last launch of each call takes one step),

@@ -478,8 +478,12 @@ __device__ __attribute__((always_inline)) inline void stepn_wave(const StepParam
 // ceil(NS / V) halo lanes on each side.  Needs nx a multiple of V (vector
 // accesses) and ny >= LY + 2 NS (a row index wraps at most once);
 // march_ok() tells.
+// FP16 storage takes two columns per lane (4-byte accesses) instead of the
+// short-segment kernel's four: its ring rows then hold as many registers as
+// FP32's, and four waves fit a SIMD (27.3 against 34.4 us per step for four
+// steps with four columns per lane).
 template <typename S, int NS> struct MTb {
-    static constexpr int V = Tb<S>::V;
+    static constexpr int V = std::is_same_v<S, _Float16> ? 2 : Tb<S>::V;
     static constexpr int H = (NS + V - 1) / V;
     static constexpr int OW = (64 - 2 * H) * V;
 };
@@ -494,7 +498,10 @@ template <typename S, int NS> struct MTb {
 // 40.5 with U = 6, LY = 24), five 43.5.  D2Q9 BGK at tau = 1/2: six steps
 // 63.1 (254 VGPRs, two waves), five 70.2-72.8, four 79.5-80.9 (the
 // short-segment kernel, three steps: 102.2).  D2Q9 MRT: five steps 86.4
-// (230 VGPRs), four 88.0-89.8, six 87.8 (three steps: 117.0).
+// (230 VGPRs), four 88.0-89.8, six 87.8 (three steps: 117.0).  D2Q5 with
+// FP16 storage, two columns per lane: five steps 27.3 / 35.0 for BGK / MRT
+// (120 VGPRs, four waves per SIMD), six 28.4 / 38.0, seven 28.9 / 39.1
+// (the short-segment kernel, three steps: 36.0 / 46.4).
 template <typename S, int Q, int KIND, int NS> struct March {
     static constexpr int LY = 20, PD = 2, U = 5;
     static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
@@ -922,10 +929,13 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
 // marching 24-row segments ran at the speed of the 6-row kernel (45.0
 // against 44.4 us per step; both are held by the memory access pattern, not
 // by their arithmetic), so the marching kernel only takes the step counts
-// that the short segments cannot afford: seven for D2Q5 (30.7 us per step
-// for BGK), six for D2Q9 BGK and five for D2Q9 MRT (see March).
+// that the short segments cannot afford: with FP32 storage seven for D2Q5
+// (30.7 us per step for BGK), six for D2Q9 BGK and five for D2Q9 MRT; five
+// for D2Q5 with FP16 storage (see March).
 template <typename S, int Q, int KIND>
-constexpr int march_steps() { return std::is_same_v<S, float> ? (Q == 5 ? 7 : KIND == 1 ? 5 : 6) : 0; }
+constexpr int march_steps() {
+    return std::is_same_v<S, float> ? (Q == 5 ? 7 : KIND == 1 ? 5 : 6) : std::is_same_v<S, _Float16> && Q == 5 ? 5 : 0;
+}
 
 // The marching kernel's step count for a grid, 0 if it does not take it.
 template <typename S, int Q>

@@ -93,7 +93,7 @@ def test_validate(lw, kw, code):
 
 
 @pytest.mark.parametrize("q,coll,prec,ns,nsm,ly", [
-    (5, "bgk", "f32", 4, 7, 20), (5, "mrt", "f32", 4, 7, 20), (5, "bgk", "f64", 4, 4, 0), (5, "mrt", "f16s", 3, 3, 0),
+    (5, "bgk", "f32", 4, 7, 20), (5, "mrt", "f32", 4, 7, 20), (5, "bgk", "f64", 4, 4, 0), (5, "mrt", "f16s", 3, 5, 20),
     (9, "bgk", "f32", 3, 6, 20), (9, "mrt", "f32", 3, 5, 20), (9, "mrt", "f64", 4, 4, 0), (9, "bgk", "f16s", 1, 1, 0)])
 def test_blocked_steps(lw, q, coll, prec, ns, nsm, ly):
     """Steps per launch of lb_step_n for each configuration: ns with the

@@ -232,3 +232,21 @@ def test_marching_kernel_shapes(q, collision, s, nx, ny):
         two = both(case, "f32")
         if nsteps == 45:
             compare(case, "f32", gpu=two)
+
+
+@pytest.mark.parametrize("collision,s", [("bgk", None), ("bgk", 0.8), ("mrt", [1, 1, 1, 1.6, 1.3])])
+@pytest.mark.parametrize("nx,ny", [(500, 30), (500, 29), (464, 31), (228, 41), (348, 71), (448, 48)])
+def test_marching_kernel_shapes_f16(collision, s, nx, ny):
+    """D2Q5 with FP16 storage through the marching kernel (five steps per
+    launch when nx is a multiple of 4 and ny >= 30; two columns per lane,
+    116 owned per strip; 20-row segments) and grids just too short for it:
+    bitwise equal to one step per launch."""
+    tau = s if isinstance(s, float) else 0.5
+    coll_s = None if isinstance(s, float) else s
+    for nsteps, src in ((33, (min(116, nx - 1), 20)), (12, (nx - 1, ny - 1))):
+        case = layered_case(nx, ny, q=5, collision=collision, tau=tau, s=coll_s, nsteps=nsteps, sponge=3)
+        case["source"] = src
+        case["wavelet"] = 1e2 * case["wavelet"]
+        case["receivers"] = np.concatenate([case["receivers"], marching_receivers(nx, ny),
+                                            np.array([src], dtype=np.int32)])
+        both(case, "f16s")
