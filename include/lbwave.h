@@ -112,7 +112,9 @@ typedef struct lb_grid lb_grid;
  *                  populations on grids with nx even, seven for D2Q5 when
  *                  ny >= 34, six for D2Q9 BGK when ny >= 32 and five for
  *                  D2Q9 MRT when ny >= 30; otherwise four for D2Q5 and
- *                  three for D2Q9; four with FP64 populations; with FP16
+ *                  three for D2Q9; with FP64 populations eight for D2Q5
+ *                  BGK when ny >= 36, seven for D2Q5 MRT when ny >= 34,
+ *                  otherwise four, and four for D2Q9; with FP16
  *                  storage five for D2Q5 when nx is a multiple of 4 and
  *                  ny >= 30, otherwise three, and one for D2Q9;
  *                  lb_blocked_steps reports the count) wherever it can (no

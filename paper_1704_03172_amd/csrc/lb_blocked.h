@@ -501,7 +501,12 @@ template <typename S, int NS> struct MTb {
 // (230 VGPRs), four 88.0-89.8, six 87.8 (three steps: 117.0).  D2Q5 with
 // FP16 storage, two columns per lane: five steps 27.3 / 35.0 for BGK / MRT
 // (120 VGPRs, four waves per SIMD), six 28.4 / 38.0, seven 28.9 / 39.1
-// (the short-segment kernel, three steps: 36.0 / 46.4).
+// (the short-segment kernel, three steps: 36.0 / 46.4).  FP64, one column
+// per lane: D2Q5 BGK eight steps 55.6 (174 VGPRs), seven 58.6, six 62.7,
+// four or five 77.5; D2Q5 MRT seven 61.6 (154 VGPRs), eight 70.0, six 64.4;
+// D2Q9 four steps 134.5 / 143.8 for BGK / MRT, five 135.4 / 144.8, three
+// 212 / 217 (the short-segment kernel, four steps: 76.5 / 79.3 for D2Q5,
+// 146.2 / 183.1 for D2Q9).
 template <typename S, int Q, int KIND, int NS> struct March {
     static constexpr int LY = 20, PD = 2, U = 5;
     static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
@@ -930,11 +935,14 @@ int64_t waves_of(int kind, int ns, int32_t nx, int32_t ny) {
 // against 44.4 us per step; both are held by the memory access pattern, not
 // by their arithmetic), so the marching kernel only takes the step counts
 // that the short segments cannot afford: with FP32 storage seven for D2Q5
-// (30.7 us per step for BGK), six for D2Q9 BGK and five for D2Q9 MRT; five
-// for D2Q5 with FP16 storage (see March).
+// (30.7 us per step for BGK), six for D2Q9 BGK and five for D2Q9 MRT; with
+// FP64 eight for D2Q5 BGK, seven for D2Q5 MRT and four for D2Q9; five for
+// D2Q5 with FP16 storage (see March).
 template <typename S, int Q, int KIND>
 constexpr int march_steps() {
-    return std::is_same_v<S, float> ? (Q == 5 ? 7 : KIND == 1 ? 5 : 6) : std::is_same_v<S, _Float16> && Q == 5 ? 5 : 0;
+    if constexpr (std::is_same_v<S, float>) return Q == 5 ? 7 : KIND == 1 ? 5 : 6;
+    else if constexpr (std::is_same_v<S, double>) return Q == 5 ? (KIND == 1 ? 7 : 8) : 4;
+    else return Q == 5 ? 5 : 0;
 }
 
 // The marching kernel's step count for a grid, 0 if it does not take it.
@@ -954,9 +962,10 @@ template <typename S, int Q>
 hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
     const int kind = step_kind(p.coll);
     const int mn = march_grid<S, Q>(kind, p.nx, p.ny);
-    if (mn > 0 && ns == mn) {
-        // the marching kernel takes its times from the params only
-        if (p.rho_out != nullptr || p.gtab != nullptr) return hipErrorInvalidValue;
+    // the marching kernel writes no rho and takes its times from the params
+    // only; launches that write rho or replay a chunk take the short-segment
+    // kernel (the same step count where both have it: FP64 D2Q9)
+    if (mn > 0 && ns == mn && p.rho_out == nullptr && p.gtab == nullptr) {
         auto launch = [&](auto kc) {
             constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
             if constexpr (MN > 0) {

@@ -191,11 +191,12 @@ def test_two_step_vs_oracle_pulse_f64():
 
 def marching_receivers(nx, ny):
     """Receivers on the strip edges of the marching kernel (owned widths 112
-    and 116 columns for seven and for five or six steps), on its 20-row
+    and 116 columns for seven and for five or six steps, 48, 50 and 56 for
+    FP64's eight, seven and four), on its 20-row
     segment edges (and 24-row ones), on the periodic seam and in the
     sponge."""
     xs = {0, 1, nx - 1, nx - 2}
-    for w in (112, 116):
+    for w in (112, 116, 48, 50, 56):
         for k in range(1, nx // w + 1):
             xs.update({k * w - 1, k * w, k * w + 1})
     ys = {0, 1, ny - 1, ny - 2}
@@ -232,6 +233,29 @@ def test_marching_kernel_shapes(q, collision, s, nx, ny):
         two = both(case, "f32")
         if nsteps == 45:
             compare(case, "f32", gpu=two)
+
+
+@pytest.mark.parametrize("q,collision,s", [(5, "bgk", None), (5, "bgk", 0.8), (5, "mrt", [1, 1, 1, 1.6, 1.3]),
+                                           (9, "bgk", None), (9, "mrt", [1, 1, 1, 2, 2, 2, 1, 1, 2])])
+@pytest.mark.parametrize("nx,ny", [(301, 36), (300, 35), (250, 34), (251, 33), (200, 28), (199, 27), (147, 61),
+                                   (96, 52)])
+def test_marching_kernel_shapes_f64(q, collision, s, nx, ny):
+    """FP64 grids that take the marching kernel (one column per lane,
+    20-row segments; eight steps per launch for D2Q5 BGK when ny >= 36,
+    seven for D2Q5 MRT when ny >= 34, four for D2Q9 when ny >= 28; odd
+    widths included) and grids just too short for it: bitwise equal to one
+    step per launch and within the FP64 bar of the oracle."""
+    tau = s if isinstance(s, float) else 0.5
+    coll_s = None if isinstance(s, float) else s
+    for nsteps, src in ((41, (min(48, nx - 1), 20)), (11, (nx - 1, ny - 1))):
+        case = layered_case(nx, ny, q=q, collision=collision, tau=tau, s=coll_s, nsteps=nsteps, sponge=3)
+        case["source"] = src
+        case["wavelet"] = 1e2 * case["wavelet"]
+        case["receivers"] = np.concatenate([case["receivers"], marching_receivers(nx, ny),
+                                            np.array([src], dtype=np.int32)])
+        two = both(case, "f64")
+        if nsteps == 41:
+            compare(case, "f64", gpu=two)
 
 
 @pytest.mark.parametrize("collision,s", [("bgk", None), ("bgk", 0.8), ("mrt", [1, 1, 1, 1.6, 1.3])])
