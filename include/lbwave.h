@@ -108,30 +108,37 @@ typedef struct lb_grid lb_grid;
  *                  two adjoint population sets).  0: no checkpoints.
  *   ckpt_capacity  checkpoint slots; a run of N steps needs N / K + 1.
  *   steps_per_launch  0 (default): lb_step_n advances several time steps
- *                  per kernel launch (temporal blocking: with FP32
- *                  populations on grids with nx even, seven for D2Q5 when
- *                  ny >= 34, six for D2Q9 BGK when ny >= 32 and five for
- *                  D2Q9 MRT when ny >= 30; otherwise four for D2Q5 and
- *                  three for D2Q9; with FP64 populations eight for D2Q5
- *                  BGK when ny >= 36, seven for D2Q5 MRT when ny >= 34,
- *                  otherwise four, and four for D2Q9; with FP16
- *                  storage five for D2Q5 when nx is a multiple of 4 and
- *                  ny >= 30, otherwise three, and one for D2Q9;
- *                  lb_blocked_steps reports the count) wherever it can (no
- *                  patch, no sum-rho recording, no checkpoint falling inside
- *                  a launch; the last launch of each call takes one step),
- *                  which divides the HBM traffic per step accordingly; the
- *                  results equal those of one step per launch bit for bit.
+ *                  per kernel launch (temporal blocking), wherever it can
+ *                  (no patch, no sum-rho recording, no checkpoint falling
+ *                  inside a launch; the last launch of each call takes one
+ *                  step), which divides the HBM traffic per step
+ *                  accordingly; the results equal those of one step per
+ *                  launch bit for bit.  The marching kernel, on grids it
+ *                  takes that are large enough to fill the GPU with its
+ *                  waves (FP32 D2Q5 from about 2300^2, D2Q9 from about
+ *                  1500^2; FP64 D2Q5 from about 1300^2, D2Q9 always; FP16
+ *                  storage from about 2300^2), takes with FP32 populations
+ *                  seven steps for D2Q5 (nx even, ny >= 34), six for D2Q9
+ *                  BGK (ny >= 32) and five for D2Q9 MRT (ny >= 30); with
+ *                  FP64 eight for D2Q5 BGK (ny >= 36), seven for D2Q5 MRT
+ *                  (ny >= 34) and four for D2Q9 (ny >= 28); with FP16
+ *                  storage five for D2Q5 (nx a multiple of 4, ny >= 30).
+ *                  Otherwise the short-segment kernel takes four steps for
+ *                  D2Q5 and for FP64, three for D2Q9 with FP32 populations
+ *                  and for D2Q5 with FP16 storage, and one for D2Q9 with
+ *                  FP16 storage.  lb_blocked_steps reports the count.
  *                  1 .. 8: at most that many steps per launch (a launch
- *                  takes 1 .. 4 steps, or the marching count offered).
+ *                  takes 1 .. 4 steps, or the marching count, which a cap
+ *                  at or above it selects on any grid the marching kernel
+ *                  takes).
  *   nbatch         independent shots sharing the grid shape (must be 1).
  *   rho_tape       1: lb_step_n also keeps the pre-collision rho of every
  *                  time 0 .. trace_capacity - 1 of the run since lb_set_state
  *                  (the workspace grows by trace_capacity rho fields), and
  *                  lb_adjoint reads it instead of recomputing segments from
- *                  checkpoints (no ckpt_every needed).  Steps are taken up to
- *                  four per launch (the kernels that write rho).  Not with a
- *                  patch.  0: off.
+ *                  checkpoints (no ckpt_every needed).  Steps per launch as
+ *                  without the tape (the multi-step kernels also write
+ *                  rho).  Not with a patch.  0: off.
  */
 typedef struct {
     int32_t nx, ny;

@@ -106,6 +106,7 @@ struct lb_batch {
     int64_t total_blocks = 0, total_waves = 0, total_mwaves = 0;
     int ns = 1;                        // steps per launch (blocked kernel if > 1)
     int nsm = 0;                       // steps of a marching round (0: none)
+    int64_t min_mwaves = 0;            // fewest marching waves for a marching round
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -244,10 +245,12 @@ int enqueue_launch(lb_batch *b, BatchParams &p, int run, int sel) {
 // Whether the marching rounds of the next k steps need the launches for
 // shots outside the marching launch, one flag per round, from the host
 // times (a shot whose shape the marching kernel does not take, or one with
-// fewer than nsm steps left at the round).
+// fewer than nsm steps left at the round).  No marching rounds (an empty
+// list) while the active shots give the marching launch fewer waves than
+// fill the GPU: the short-segment launches are faster then.
 std::vector<char> round_needs(const lb_batch *b, int64_t k) {
     std::vector<char> need;
-    if (b->nsm <= 0 || b->total_mwaves <= 0) return need;
+    if (b->nsm <= 0 || b->total_mwaves <= 0 || b->total_mwaves < b->min_mwaves) return need;
     std::vector<int64_t> t(b->ht);
     for (int64_t r = 0; r + b->nsm <= k; r += b->nsm) {
         char nd = 0;
@@ -378,8 +381,12 @@ int lb_batch_create(const lb_grid_desc *scheme, int32_t max_shots, void *d_works
     if (scheme->steps_per_launch > 0) b->ns = std::min(b->ns, scheme->steps_per_launch);
     // marching rounds: the marching kernel's step count for this scheme (a
     // shape it takes), unless steps_per_launch caps it lower
+    // and, as for a single grid, a cap at or above that count asks for the
+    // marching rounds however few waves the active shots give them
     b->nsm = lbw::stepn_march(b->storage, b->q, lbw::step_kind(b->coll), 1024, 1024);
+    b->min_mwaves = lbw::stepn_march_min_waves(b->storage, b->q, lbw::step_kind(b->coll));
     if (scheme->steps_per_launch > 0 && scheme->steps_per_launch < b->nsm) b->nsm = 0;
+    if (scheme->steps_per_launch > 0) b->min_mwaves = 0;
     char *ws = (char *)d_workspace;
     b->d_table = (ShotEntry *)(ws + L.table);
     b->d_state = (ShotState *)(ws + L.state);

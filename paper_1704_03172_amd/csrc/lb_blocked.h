@@ -510,6 +510,19 @@ template <typename S, int NS> struct MTb {
 template <typename S, int Q, int KIND, int NS> struct March {
     static constexpr int LY = 20, PD = 2, U = 5;
     static constexpr int CR = NS <= 4 ? 4 : 8;   // c^2 ring rows (>= NS)
+    // Fewest waves for which a single grid's launch plan prefers the
+    // marching kernel.  A wave's walk has a latency floor (LY + 2 NS rows one
+    // after the other), so a grid with few waves leaves the GPU idle and the
+    // short-segment kernel, with more and shorter waves, is faster.  Measured
+    // crossovers (square grids): FP32 D2Q5 between 2048^2 (1,957 waves:
+    // 14.9 against 13.5 us per step) and 2560^2 (2,944: 17.2 against 18.6);
+    // FP32 D2Q9 near 1536^2 (1,078 waves: 17.5 / 17.2); FP64 D2Q5 between
+    // 1024^2 (1,144: 9.3 / 7.8) and 1536^2 (2,464: 13.7 / 14.5); FP16 storage
+    // between 2048^2 (1,854: 15.0 / 13.6) and 2560^2 (2,944: 16.7 / 17.5).
+    // FP64 D2Q9 shares its step count with the short-segment kernel and
+    // always marches.  The batched executor, whose marching launch covers
+    // every shot's waves at once, marches whatever a shot's size.
+    static constexpr int64_t MIN_WAVES = std::is_same_v<S, double> ? (Q == 5 ? 1800 : 0) : Q == 5 ? 2500 : 1100;
 };
 
 template <typename S, int Q, int KIND, int NS>
@@ -561,7 +574,9 @@ __device__ inline A &pick8(A &a0, A &a1, A &a2, A &a3, A &a4, A &a5, A &a6, A &a
     else return pick4<I - 4>(a4, a5, a6, a7);
 }
 
-template <typename S, int Q, int KIND, int NS, typename RARE>
+// RHO: also write rho of each stage's time at the owned nodes (p.rho_out,
+// p.rho_stride), summed as the one-step kernel sums it.
+template <typename S, int Q, int KIND, int NS, bool RHO = false, typename RARE>
 __device__ __attribute__((always_inline)) inline void march_wave(const StepParams &p, int wave,
                                                                  typename Tr<S>::T *c2ring, RARE rare) {
     using T = typename Tr<S>::T;
@@ -668,6 +683,21 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
         }
         T g[Q][V];
         pull_row2<T, Q, V>(A[SU], A[SM], A[SD], g);
+        if constexpr (RHO) {   // rho of time n+st at the owned nodes
+            if (owned_row && own[0]) {
+                typedef typename LaneVec<V, T>::type rt;
+                rt t;
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    T rho = T(0);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) rho += g[i][j];
+                    t[j] = rho;
+                }
+                T *rr = reinterpret_cast<T *>(p.rho_out) + (int64_t)(st - 1) * p.rho_stride + (int64_t)gm * nx;
+                *(GlobalPtr<rt>)at_lane<rt>(rr, xv) = t;
+            }
+        }
         int rb = 0, re = 0;
         if (has_rec && owned_row) {
             rb = __builtin_amdgcn_readlane(rowv, m - NS);
@@ -787,6 +817,18 @@ __global__ __launch_bounds__(kT2Block) void k_stepn_march(StepParams p) {
     __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     march_wave<S, Q, KIND, NS>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib], RareKernarg());
+}
+
+// The marching launch that also writes rho of every stage's time (the
+// forward run that keeps the rho tape, the adjoint's recompute): a kernel of
+// its own, so that the forward kernel carries none of its registers.
+template <typename S, int Q, int KIND, int NS>
+__global__ __launch_bounds__(kT2Block) void k_stepn_march_rho(StepParams p) {
+    using T = typename Tr<S>::T;
+    constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
+    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    march_wave<S, Q, KIND, NS, true>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib], RareKernarg());
 }
 
 template <typename S, int Q, int KIND, bool VEC, int NS, bool RHO>
@@ -945,13 +987,29 @@ constexpr int march_steps() {
     else return Q == 5 ? 5 : 0;
 }
 
-// The marching kernel's step count for a grid, 0 if it does not take it.
+// The marching kernel's step count for a grid, 0 if it does not take it
+// (pref: also 0 if the grid has fewer waves than the kernel's MIN_WAVES).
 template <typename S, int Q>
-int march_grid(int kind, int32_t nx, int32_t ny) {
+int march_grid(int kind, int32_t nx, int32_t ny, bool pref = false) {
     auto one = [&](auto kc) {
         constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
         if constexpr (MN == 0) return 0;
-        else return march_ok<S, Q, KK, MN>(nx, ny) ? MN : 0;
+        else {
+            if (!march_ok<S, Q, KK, MN>(nx, ny)) return 0;
+            return !pref || march_waves<S, Q, KK, MN>(nx, ny) >= March<S, Q, KK, MN>::MIN_WAVES ? MN : 0;
+        }
+    };
+    return kind == 1 ? one(std::integral_constant<int, 1>())
+         : kind == 2 ? one(std::integral_constant<int, 2>()) : one(std::integral_constant<int, 0>());
+}
+
+// MIN_WAVES of the marching kernel for a collision kind (0: none).
+template <typename S, int Q>
+int64_t march_min_waves_of(int kind) {
+    auto one = [&](auto kc) -> int64_t {
+        constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
+        if constexpr (MN == 0) return 0;
+        else return March<S, Q, KK, MN>::MIN_WAVES;
     };
     return kind == 1 ? one(std::integral_constant<int, 1>())
          : kind == 2 ? one(std::integral_constant<int, 2>()) : one(std::integral_constant<int, 0>());
@@ -962,16 +1020,21 @@ template <typename S, int Q>
 hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
     const int kind = step_kind(p.coll);
     const int mn = march_grid<S, Q>(kind, p.nx, p.ny);
-    // the marching kernel writes no rho and takes its times from the params
-    // only; launches that write rho or replay a chunk take the short-segment
-    // kernel (the same step count where both have it: FP64 D2Q9)
-    if (mn > 0 && ns == mn && p.rho_out == nullptr && p.gtab == nullptr) {
+    // the marching kernel takes its times from the params only; a launch of
+    // a captured chunk takes the short-segment kernel, and so does a launch
+    // whose step count both kernels have (FP64 D2Q9) on a grid the marching
+    // kernel would leave underfilled
+    const int sm = kind == 1 ? tn_max<S, Q, 1>() : kind == 2 ? tn_max<S, Q, 2>() : tn_max<S, Q, 0>();
+    if (mn > 0 && ns == mn && p.gtab == nullptr && (ns > sm || march_grid<S, Q>(kind, p.nx, p.ny, true) == mn)) {
         auto launch = [&](auto kc) {
             constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
             if constexpr (MN > 0) {
                 const int64_t nw = march_waves<S, Q, KK, MN>(p.nx, p.ny);
                 const dim3 mgrid((unsigned)((nw + kT2Block / 64 - 1) / (kT2Block / 64)));
-                hipLaunchKernelGGL((k_stepn_march<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
+                if (p.rho_out != nullptr)
+                    hipLaunchKernelGGL((k_stepn_march_rho<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
+                else
+                    hipLaunchKernelGGL((k_stepn_march<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
@@ -1078,8 +1141,11 @@ int64_t march_waves_of(int kind, int32_t nx, int32_t ny) {
     hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s) {                    \
         return stepn_launch<SS, QQ>(p, ns, s);                                                      \
     }                                                                                               \
-    int march_steps_##NAME(int kind, int32_t nx, int32_t ny) {                                      \
-        return march_grid<SS, QQ>(kind, nx, ny);                                                    \
+    int march_steps_##NAME(int kind, int32_t nx, int32_t ny, bool pref) {                           \
+        return march_grid<SS, QQ>(kind, nx, ny, pref);                                              \
+    }                                                                                               \
+    int64_t march_min_waves_##NAME(int kind) {                                                      \
+        return march_min_waves_of<SS, QQ>(kind);                                                    \
     }                                                                                               \
     hipError_t launch_stepn_march_batch_##NAME(const BatchParams &bp, int64_t nwaves, hipStream_t s) {   \
         return stepn_march_batch_launch<SS, QQ>(bp, nwaves, s);                                     \
@@ -1093,7 +1159,8 @@ int64_t march_waves_of(int kind, int32_t nx, int32_t ny) {
 
 #define LBW_BLOCKED_DECL(NAME)                                                                      \
     hipError_t launch_stepn_##NAME(const StepParams &p, int ns, hipStream_t s);                     \
-    int march_steps_##NAME(int kind, int32_t nx, int32_t ny);                                       \
+    int march_steps_##NAME(int kind, int32_t nx, int32_t ny, bool pref);                            \
+    int64_t march_min_waves_##NAME(int kind);                                                       \
     hipError_t launch_stepn_batch_##NAME(const BatchParams &bp, int ns, int64_t nwaves, hipStream_t s); \
     hipError_t launch_stepn_march_batch_##NAME(const BatchParams &bp, int64_t nwaves, hipStream_t s);   \
     int64_t march_waves_##NAME(int kind, int32_t nx, int32_t ny);

@@ -105,16 +105,25 @@ int stepn_graph_steps(int storage, int q, int kind, int32_t nx) {
     });
 }
 
-int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny) {
+int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny, bool pref) {
     if (nx < 1 || ny < 1) return 0;
-    if (storage == ST_F32) return q == 5 ? march_steps_f32_q5(kind, nx, ny) : march_steps_f32_q9(kind, nx, ny);
-    if (storage == ST_F64) return q == 5 ? march_steps_f64_q5(kind, nx, ny) : march_steps_f64_q9(kind, nx, ny);
-    if (storage == ST_F16 && q == 5) return march_steps_f16_q5(kind, nx, ny);
+    if (storage == ST_F32)
+        return q == 5 ? march_steps_f32_q5(kind, nx, ny, pref) : march_steps_f32_q9(kind, nx, ny, pref);
+    if (storage == ST_F64)
+        return q == 5 ? march_steps_f64_q5(kind, nx, ny, pref) : march_steps_f64_q9(kind, nx, ny, pref);
+    if (storage == ST_F16 && q == 5) return march_steps_f16_q5(kind, nx, ny, pref);
     return 0;
 }
 
-int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny) {
-    return std::max(stepn_max(storage, q, kind == 1 ? 1 : 0), stepn_march(storage, q, kind, nx, ny));
+int64_t stepn_march_min_waves(int storage, int q, int kind) {
+    if (storage == ST_F32) return q == 5 ? march_min_waves_f32_q5(kind) : march_min_waves_f32_q9(kind);
+    if (storage == ST_F64) return q == 5 ? march_min_waves_f64_q5(kind) : march_min_waves_f64_q9(kind);
+    if (storage == ST_F16 && q == 5) return march_min_waves_f16_q5(kind);
+    return 0;
+}
+
+int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny, bool pref) {
+    return std::max(stepn_max(storage, q, kind == 1 ? 1 : 0), stepn_march(storage, q, kind, nx, ny, pref));
 }
 
 int stepn_round(int storage, int q, int kind, int32_t nx, int32_t ny, int ns) {
@@ -132,7 +141,7 @@ int64_t stepn_waves(int storage, int q, int kind, int ns, int32_t nx, int32_t ny
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s) {
     if (p.nx < 1 || p.ny < 1 || (p.q != 5 && p.q != 9) || ns < 2 || p.nrun != ns) return hipErrorInvalidValue;
     const int kind = step_kind(p.coll);
-    const bool march = ns == stepn_march(storage, p.q, kind, p.nx, p.ny) && p.rho_out == nullptr;
+    const bool march = ns == stepn_march(storage, p.q, kind, p.nx, p.ny);
     if (!march && ns > stepn_max(storage, p.q, p.coll.kind)) return hipErrorInvalidValue;
     if (storage == ST_F32) return p.q == 5 ? launch_stepn_f32_q5(p, ns, s) : launch_stepn_f32_q9(p, ns, s);
     if (storage == ST_F64) return p.q == 5 ? launch_stepn_f64_q5(p, ns, s) : launch_stepn_f64_q9(p, ns, s);

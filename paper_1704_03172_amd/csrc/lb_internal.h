@@ -264,7 +264,7 @@ hipError_t launch_step(int storage, const StepParams &p, bool pull,
 // time n + s (s = 1..ns) goes to p.rho_out + (s - 1) * p.rho_stride.  No
 // reduction partials, snapshot or interface work.
 // 2 <= ns <= stepn_max(storage, p.q, p.coll.kind), or ns = stepn_march(...)
-// without rho_out or gtab; with gtab ns = stepn_graph_steps(...) only.
+// without gtab; with gtab ns = stepn_graph_steps(...) only.
 hipError_t launch_stepn(int storage, const StepParams &p, int ns, hipStream_t s);
 int stepn_max(int storage, int q, int kind);   // steps per launch the blocked kernel offers (1: none)
 // Steps of the multi-step launches of a captured chunk (p.gtab set): the
@@ -273,10 +273,16 @@ int stepn_max(int storage, int q, int kind);   // steps per launch the blocked k
 int stepn_graph_steps(int storage, int q, int kind, int32_t nx);
 // Steps per launch of the marching kernel for an nx x ny grid (kind:
 // step_kind()), 0 where it does not apply; it takes exactly that count.
-int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny);
-// Most steps one launch takes on an nx x ny grid, and the largest step count
-// a launch can take that is at most ns (>= 1); kind is step_kind().
-int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny);
+// pref: also 0 where a single grid of that size would leave the GPU
+// underfilled with the marching kernel's waves (the launch plan's default).
+int stepn_march(int storage, int q, int kind, int32_t nx, int32_t ny, bool pref = false);
+// Fewest waves for which a marching launch fills the GPU (the threshold of
+// pref above; the batched executor applies it to a round's waves).
+int64_t stepn_march_min_waves(int storage, int q, int kind);
+// Most steps one launch takes on an nx x ny grid (pref: as the default
+// launch plan chooses), and the largest step count a launch can take that
+// is at most ns (>= 1); kind is step_kind().
+int stepn_max_grid(int storage, int q, int kind, int32_t nx, int32_t ny, bool pref = false);
 int stepn_round(int storage, int q, int kind, int32_t nx, int32_t ny, int ns);
 int64_t step_blocks(int storage, int32_t nx, int32_t ny, bool pull);
 // Sum of the nblocks partials to out[0], or (gtab set: a replayed graph) to

@@ -628,11 +628,12 @@ int lb_blocked_steps(const lb_grid_desc *d, int32_t *ns) {
     int rc = validate(d);
     if (rc) return rc;
     const int sk = lbw::step_kind(lbw::make_collision(d));
-    int m = lbw::stepn_max_grid(storage_kind(d->precision), d->lattice, sk, d->nx, d->ny);
+    const int st = storage_kind(d->precision);
+    int m = lbw::stepn_max_grid(st, d->lattice, sk, d->nx, d->ny, true);
+    if (d->steps_per_launch > 0)   // an explicit cap may ask for the marching kernel at any size
+        m = lbw::stepn_round(st, d->lattice, sk, d->nx, d->ny,
+                             std::min(lbw::stepn_max_grid(st, d->lattice, sk, d->nx, d->ny), (int)d->steps_per_launch));
     if (d->patch_enable) m = 1;
-    if (d->steps_per_launch > 0)
-        m = lbw::stepn_round(storage_kind(d->precision), d->lattice, sk, d->nx, d->ny,
-                             std::min(m, (int)d->steps_per_launch));
     *ns = m;
     return LB_OK;
 }
@@ -811,18 +812,19 @@ int lb_record_sum_rho(lb_grid *h, double *d_sum) {
     return LB_OK;
 }
 
-// Steps per launch of the blocked kernels for this grid (1: none), capped by
-// the descriptor's steps_per_launch: up to stepn_max steps, and on grids
-// that the marching kernel takes also its (larger) step count.
+// Steps per launch of the blocked kernels for this grid (1: none): up to
+// stepn_max steps, and on grids that the marching kernel takes and fills
+// with its waves also its (larger) step count; a descriptor's
+// steps_per_launch caps it, and may ask for the marching kernel on any grid
+// it takes.
 int blocked_max(const lb_grid *h) {
     if (h->patch) return 1;
     const int sk = lbw::step_kind(h->coll);
-    int ns = lbw::stepn_max_grid(h->storage, h->q, sk, h->d.nx, h->d.ny);
-    if (h->d.steps_per_launch > 0)
-        ns = lbw::stepn_round(h->storage, h->q, sk, h->d.nx, h->d.ny, std::min(ns, h->d.steps_per_launch));
-    if (h->tape)   // the kernels that also write rho take up to stepn_max steps
+    int ns = lbw::stepn_max_grid(h->storage, h->q, sk, h->d.nx, h->d.ny, true);
+    if (h->d.steps_per_launch > 0)   // an explicit cap may ask for the marching kernel at any size
         ns = lbw::stepn_round(h->storage, h->q, sk, h->d.nx, h->d.ny,
-                              std::min(ns, lbw::stepn_max(h->storage, h->q, h->d.collision)));
+                              std::min(lbw::stepn_max_grid(h->storage, h->q, sk, h->d.nx, h->d.ny),
+                                       h->d.steps_per_launch));
     return ns;
 }
 
@@ -1193,15 +1195,15 @@ int lb_adjoint(lb_grid *h, const void *d_res, int64_t nt, double *d_grad) {
             p.dst = g.prevp();
             p.s_n = source_at(h, m);
             p.rho_out = (char *)h->seg + (size_t)(m - a) * n_nodes * tsz;
-            // (the rho-writing kernel takes up to stepn_max steps)
-            const int ns = pull ? (int)std::min<int64_t>(
-                                      std::min(blocked_max(h), lbw::stepn_max(h->storage, h->q, h->d.collision)),
-                                      b - m + 1)
+            // (rounded down to a count a kernel takes)
+            const int ns = pull ? lbw::stepn_round(h->storage, h->q, lbw::step_kind(h->coll), h->d.nx, h->d.ny,
+                                                   (int)std::min<int64_t>(blocked_max(h), b - m + 1))
                                 : 1;
             if (ns > 1) {
                 p.s_n2 = source_at(h, m + 1);
                 p.s_n3 = source_at(h, m + 2);
                 p.s_n4 = source_at(h, m + 3);
+                for (int k = 0; k < 4; ++k) p.s_more[k] = source_at(h, m + 4 + k);
                 p.nrun = ns;
                 p.rho_stride = n_nodes;
                 LB_TRY(h, lbw::launch_stepn(h->storage, p, ns, h->stream));

@@ -98,17 +98,23 @@ def test_validate(lw, kw, code):
 def test_blocked_steps(lw, q, coll, prec, ns, nsm, ly):
     """Steps per launch of lb_step_n for each configuration: ns with the
     short-segment kernel, nsm where the marching kernel (segments of ly
-    rows) takes the grid (FP32, ny >= ly + 2 nsm: seven steps for D2Q5, six
-    for D2Q9 BGK, five for D2Q9 MRT); the cap of steps_per_launch (rounded
-    down to a count a kernel takes), one step with a patch, and the
-    validation errors."""
+    rows) takes the grid (ny >= ly + 2 nsm; FP32: seven steps for D2Q5, six
+    for D2Q9 BGK, five for D2Q9 MRT) and, by default, only where the grid
+    fills the GPU with its waves (a 4096^2 grid does, a 64^2 one does not,
+    except FP64 D2Q9, whose two kernels take the same count); a cap of
+    steps_per_launch at or above nsm asks for it on any grid it takes; the
+    cap (rounded down to a count a kernel takes), one step with a patch,
+    and the validation errors."""
     kw = dict(nx=64, ny=64, lattice=q, collision=coll, precision=prec, s=[1, 1, 1, 2, 2, 2, 1, 1, 2][:q])
-    assert lw.blocked_steps(**kw) == nsm
+    assert lw.blocked_steps(**dict(kw, nx=4096, ny=4096)) == nsm
+    assert lw.blocked_steps(**kw) == ns
+    cap8 = dict(kw, steps_per_launch=8)
+    assert lw.blocked_steps(**cap8) == nsm
     if ly:
-        assert lw.blocked_steps(**dict(kw, ny=ly + 2 * nsm)) == nsm
-        assert lw.blocked_steps(**dict(kw, ny=ly + 2 * nsm - 1)) == ns   # too short for the marching kernel
+        assert lw.blocked_steps(**dict(cap8, ny=ly + 2 * nsm)) == nsm
+        assert lw.blocked_steps(**dict(cap8, ny=ly + 2 * nsm - 1)) == ns   # too short for the marching kernel
     # odd width: no vector accesses (FP64 takes one column per lane anyway)
-    assert lw.blocked_steps(**dict(kw, nx=63)) == (nsm if prec == "f64" else ns)
+    assert lw.blocked_steps(**dict(cap8, nx=63)) == (nsm if prec == "f64" else ns)
     for cap in range(1, 9):
         want = nsm if cap >= nsm else min(cap, ns)
         assert lw.blocked_steps(steps_per_launch=cap, **kw) == want

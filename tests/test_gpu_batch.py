@@ -58,18 +58,22 @@ def run_batch(schedule, tick, use_graph=True, max_shots=4, steps_per_launch=0, *
     return out
 
 
-def test_alone_vs_mix_bitwise():
-    alone = {i: run_batch([(0, s)], tick=7)[0] for i, s in enumerate(SHOTS)}
-    mix = run_batch([(0, SHOTS[0]), (2, SHOTS[1]), (5, SHOTS[2]), (1, SHOTS[3])], tick=11)
+@pytest.mark.parametrize("spl", [0, 8])
+def test_alone_vs_mix_bitwise(spl):
+    """spl 8 asks for the marching rounds, which these small shots do not
+    fill by default."""
+    alone = {i: run_batch([(0, s)], tick=7, steps_per_launch=spl)[0] for i, s in enumerate(SHOTS)}
+    mix = run_batch([(0, SHOTS[0]), (2, SHOTS[1]), (5, SHOTS[2]), (1, SHOTS[3])], tick=11, steps_per_launch=spl)
     for i in range(4):
         assert np.abs(alone[i]).max() > 0
         np.testing.assert_array_equal(alone[i], mix[i])
 
 
-def test_graph_replays_match_eager_launches():
+@pytest.mark.parametrize("spl", [0, 8])
+def test_graph_replays_match_eager_launches(spl):
     sched = [(0, SHOTS[0]), (1, SHOTS[2]), (3, SHOTS[1])]
-    g = run_batch(sched, tick=9, use_graph=True)
-    e = run_batch(sched, tick=9, use_graph=False)
+    g = run_batch(sched, tick=9, use_graph=True, steps_per_launch=spl)
+    e = run_batch(sched, tick=9, use_graph=False, steps_per_launch=spl)
     for i in range(3):
         np.testing.assert_array_equal(g[i], e[i])
 
@@ -83,9 +87,11 @@ def test_two_step_batch_equals_one_step_batch(tick):
     sched = [(0, SHOTS[0]), (1, SHOTS[3]), (2, SHOTS[1]), (2, SHOTS[2]), (0, shot(130, 70, 151, 5))]
     a = run_batch(sched, tick=tick, steps_per_launch=1, max_shots=5)
     b = run_batch(sched, tick=tick, max_shots=5)
+    c = run_batch(sched, tick=tick, max_shots=5, steps_per_launch=8)   # marching rounds
     for i in range(5):
         assert np.abs(a[i]).max() > 0
         np.testing.assert_array_equal(a[i], b[i])
+        np.testing.assert_array_equal(a[i], c[i])
 
 
 @pytest.mark.parametrize("scheme", [dict(lattice=9, collision="bgk"),
@@ -97,7 +103,7 @@ def test_batched_marching_other_schemes(scheme):
     short, odd width) in the same ticks: the bits of one step per launch."""
     sched = [(0, SHOTS[0]), (1, SHOTS[3]), (2, SHOTS[1]), (0, shot(130, 70, 151, 5)), (1, shot(97, 40, 120, 6))]
     a = run_batch(sched, tick=23, steps_per_launch=1, max_shots=5, **scheme)
-    b = run_batch(sched, tick=23, max_shots=5, **scheme)
+    b = run_batch(sched, tick=23, max_shots=5, steps_per_launch=8, **scheme)
     for i in range(len(sched)):
         assert np.abs(a[i]).max() > 0
         np.testing.assert_array_equal(a[i], b[i])

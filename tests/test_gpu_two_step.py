@@ -230,7 +230,7 @@ def test_marching_kernel_shapes(q, collision, s, nx, ny):
         case["wavelet"] = 1e2 * case["wavelet"]
         case["receivers"] = np.concatenate([case["receivers"], marching_receivers(nx, ny),
                                             np.array([src], dtype=np.int32)])
-        two = both(case, "f32")
+        two = both(case, "f32", spl=8)   # the marching kernel on grids of any size
         if nsteps == 45:
             compare(case, "f32", gpu=two)
 
@@ -253,7 +253,7 @@ def test_marching_kernel_shapes_f64(q, collision, s, nx, ny):
         case["wavelet"] = 1e2 * case["wavelet"]
         case["receivers"] = np.concatenate([case["receivers"], marching_receivers(nx, ny),
                                             np.array([src], dtype=np.int32)])
-        two = both(case, "f64")
+        two = both(case, "f64", spl=8)
         if nsteps == 41:
             compare(case, "f64", gpu=two)
 
@@ -273,4 +273,4 @@ def test_marching_kernel_shapes_f16(collision, s, nx, ny):
         case["wavelet"] = 1e2 * case["wavelet"]
         case["receivers"] = np.concatenate([case["receivers"], marching_receivers(nx, ny),
                                             np.array([src], dtype=np.int32)])
-        both(case, "f16s")
+        both(case, "f16s", spl=8)
