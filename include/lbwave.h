@@ -366,12 +366,15 @@ const char *lb_status_string(int code);
 /* ---- batched executor (serving many shots at once) --------------------
  *
  * Many independent shots (grids of different sizes, each with its own medium,
- * source, receivers and step count) advance together: one launch covers up
- * to four time steps (as lb_blocked_steps gives for the scheme, see
- * lb_grid_desc) of every active shot, a shot with fewer steps left taking
- * those, and the shot's time and buffer
- * parity live in device memory, so a tick of k steps is captured once as a
- * HIP graph and replayed until the set of shots changes.  Each shot computes
+ * source, receivers and step count) advance together.  Where the scheme has
+ * a marching kernel (see lb_grid_desc) and the active shots give it enough
+ * waves together (or steps_per_launch asks for it), one marching launch
+ * advances every shot of a shape it takes by its step count; the other
+ * shots, and every shot otherwise, take launches of up to four steps (the
+ * short-segment kernel's count), a shot with fewer steps left taking those.
+ * The shots' times and buffer parities live in device memory, so a tick of
+ * k steps is captured once as a HIP graph and replayed until the set of
+ * shots changes.  Each shot computes
  * exactly what an lb_grid with the same parameters computes (same per-node
  * update), bitwise, whatever its batch mates.  Shots start at rest.  With
  * graphs on, a fixed block of steps is captured per set of active shots and
