@@ -34,6 +34,12 @@ namespace {
 // so the result equals NS launches of the one-step kernel bit for bit.  Only
 // rows and columns the wave owns are recorded.
 constexpr int kT2Block = 256;
+// Block of the marching kernels: two waves for FP32 (measured at 4096^2:
+// 30.48 against 30.71 us per step for four-wave blocks of D2Q5 BGK, 34.80
+// for eight), four for FP16 storage and FP64 (FP16 D2Q5 BGK: 583 against
+// 607 GLUPS with two-wave blocks).
+template <typename S>
+constexpr int march_block() { return std::is_same_v<S, float> ? 128 : 256; }
 
 constexpr int kT2Halo = 4;    // halo lanes per side
 
@@ -811,24 +817,24 @@ __device__ __attribute__((always_inline)) inline void march_wave(const StepParam
 }
 
 template <typename S, int Q, int KIND, int NS>
-__global__ __launch_bounds__(kT2Block) void k_stepn_march(StepParams p) {
+__global__ __launch_bounds__(march_block<S>()) void k_stepn_march(StepParams p) {
     using T = typename Tr<S>::T;
     constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
-    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    __shared__ T c2ring[march_block<S>() / 64][CR * 64 * V];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    march_wave<S, Q, KIND, NS>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib], RareKernarg());
+    march_wave<S, Q, KIND, NS>(p, xcd_block() * (march_block<S>() / 64) + wib, c2ring[wib], RareKernarg());
 }
 
 // The marching launch that also writes rho of every stage's time (the
 // forward run that keeps the rho tape, the adjoint's recompute): a kernel of
 // its own, so that the forward kernel carries none of its registers.
 template <typename S, int Q, int KIND, int NS>
-__global__ __launch_bounds__(kT2Block) void k_stepn_march_rho(StepParams p) {
+__global__ __launch_bounds__(march_block<S>()) void k_stepn_march_rho(StepParams p) {
     using T = typename Tr<S>::T;
     constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
-    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    __shared__ T c2ring[march_block<S>() / 64][CR * 64 * V];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    march_wave<S, Q, KIND, NS, true>(p, xcd_block() * (kT2Block / 64) + wib, c2ring[wib], RareKernarg());
+    march_wave<S, Q, KIND, NS, true>(p, xcd_block() * (march_block<S>() / 64) + wib, c2ring[wib], RareKernarg());
 }
 
 template <typename S, int Q, int KIND, bool VEC, int NS, bool RHO>
@@ -904,12 +910,12 @@ void k_stepn_batch(BatchParams bp) {
 // mprefix[a] <= w < mprefix[a+1] and walks that shot's grid with the params
 // image of the round (shots that sit the round out have no waves of use).
 template <typename S, int Q, int KIND, int NS>
-__global__ __launch_bounds__(kT2Block) void k_stepn_march_batch(BatchParams bp, const StepParams *__restrict__ img) {
+__global__ __launch_bounds__(march_block<S>()) void k_stepn_march_batch(BatchParams bp, const StepParams *__restrict__ img) {
     using T = typename Tr<S>::T;
     constexpr int CR = March<S, Q, KIND, NS>::CR, V = MTb<S, NS>::V;
-    __shared__ T c2ring[kT2Block / 64][CR * 64 * V];
+    __shared__ T c2ring[march_block<S>() / 64][CR * 64 * V];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t w = (int64_t)xcd_block() * (kT2Block / 64) + wib;
+    const int64_t w = (int64_t)xcd_block() * (march_block<S>() / 64) + wib;
     if (w >= bp.mprefix[bp.nact]) return;
     int lo = 0, hi = bp.nact - 1;
     while (lo < hi) {
@@ -1030,11 +1036,11 @@ hipError_t stepn_launch(const StepParams &p, int ns, hipStream_t s) {
             constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
             if constexpr (MN > 0) {
                 const int64_t nw = march_waves<S, Q, KK, MN>(p.nx, p.ny);
-                const dim3 mgrid((unsigned)((nw + kT2Block / 64 - 1) / (kT2Block / 64)));
+                const dim3 mgrid((unsigned)((nw + march_block<S>() / 64 - 1) / (march_block<S>() / 64)));
                 if (p.rho_out != nullptr)
-                    hipLaunchKernelGGL((k_stepn_march_rho<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
+                    hipLaunchKernelGGL((k_stepn_march_rho<S, Q, KK, MN>), mgrid, dim3(march_block<S>()), 0, s, p);
                 else
-                    hipLaunchKernelGGL((k_stepn_march<S, Q, KK, MN>), mgrid, dim3(kT2Block), 0, s, p);
+                    hipLaunchKernelGGL((k_stepn_march<S, Q, KK, MN>), mgrid, dim3(march_block<S>()), 0, s, p);
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
@@ -1104,12 +1110,12 @@ hipError_t stepn_batch_launch(const BatchParams &bp, int ns, int64_t nwaves, hip
 
 template <typename S, int Q>
 hipError_t stepn_march_batch_launch(const BatchParams &bp, int64_t nwaves, hipStream_t s) {
-    const dim3 grid((unsigned)((nwaves + kT2Block / 64 - 1) / (kT2Block / 64)));
+    const dim3 grid((unsigned)((nwaves + march_block<S>() / 64 - 1) / (march_block<S>() / 64)));
     const int kind = step_kind(bp.coll);
     auto launch = [&](auto kc) {
         constexpr int KK = decltype(kc)::value, MN = march_steps<S, Q, KK>();
         if constexpr (MN > 0) {
-            hipLaunchKernelGGL((k_stepn_march_batch<S, Q, KK, MN>), grid, dim3(kT2Block), 0, s, bp,
+            hipLaunchKernelGGL((k_stepn_march_batch<S, Q, KK, MN>), grid, dim3(march_block<S>()), 0, s, bp,
                                (const StepParams *)bp.img);
             return hipGetLastError();
         }
