@@ -115,9 +115,9 @@ typedef struct lb_grid lb_grid;
  *                  accordingly; the results equal those of one step per
  *                  launch bit for bit.  The marching kernel, on grids it
  *                  takes that are large enough to fill the GPU with its
- *                  waves (FP32 D2Q5 from about 2300^2, D2Q9 from about
- *                  1500^2; FP64 D2Q5 from about 1300^2, D2Q9 always; FP16
- *                  storage from about 2300^2), takes with FP32 populations
+ *                  waves (FP32 D2Q5 from about 2350^2, D2Q9 from about
+ *                  1570^2; FP64 D2Q5 from about 1300^2, D2Q9 always; FP16
+ *                  storage from about 2400^2), takes with FP32 populations
  *                  seven steps for D2Q5 (nx even, ny >= 34), six for D2Q9
  *                  BGK (ny >= 32) and five for D2Q9 MRT (ny >= 30); with
  *                  FP64 eight for D2Q5 BGK (ny >= 36), seven for D2Q5 MRT
